@@ -1,0 +1,162 @@
+"""TEST INFRASTRUCTURE ONLY -- the oracle.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding in ``paper_1605_01244_amd``) never imports it, and this
+package imports nothing from there.
+
+Two parts:
+
+* ``ndft_*`` -- plain FP64 direct sums (the definition of the NFFT problem,
+  Sec. 2.2.1, evaluated in the one-loop order of eq. (Fs)), in C
+  (``oracle/ndft.c``) with POSIX threads, reached through ctypes.  These are
+  the reference every GPU result is judged against.
+* ``oracle.nfft_steps`` -- a plain numpy FP64 statement of the windowed
+  algorithm the GPU implements (deconvolve, oversampled FFT, window sum),
+  used to check the GPU stages one at a time.
+
+Pins for both live in ``tests/test_oracle_*.py`` (closed forms, library
+special cases, invariants, brute force, error bounds).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ndft.c")
+_LIB = os.path.join(_HERE, "libndft.so")
+
+# The oracle is built for the plain x86-64 baseline (no -march=native) so the
+# library built here also runs on a host with a different CPU.
+_CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-pthread"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ``ndft.c`` into ``libndft.so`` with gcc (always recompiles)."""
+    cmd = ["gcc", *_CFLAGS, _SRC, "-o", _LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_ndft_trafo.argtypes = [i64p, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
+    lib.oracle_ndft_grad.argtypes = [i64p, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
+    lib.oracle_ndft_adjoint.argtypes = [i64p, ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+    for fn in (lib.oracle_ndft_trafo, lib.oracle_ndft_grad, lib.oracle_ndft_adjoint):
+        fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def default_threads() -> int:
+    env = os.environ.get("ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _shape3(N) -> np.ndarray:
+    N = np.asarray(N, dtype=np.int64).reshape(3)
+    if np.any(N < 2) or np.any(N % 2):
+        raise ValueError(f"N must hold three even sizes >= 2, got {N.tolist()}")
+    return np.ascontiguousarray(N)
+
+
+def _points(x) -> np.ndarray:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if x.ndim != 2 or x.shape[1] != 3:
+        raise ValueError("points must have shape (M, 3)")
+    return x
+
+
+def ndft_trafo(fhat: np.ndarray, x: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """f_j = sum_{k in I_N} fhat_k exp(-2 pi i k.x_j)  (Sec. 2.2.1, eq. (Fs) order).
+
+    ``fhat``: complex (N0, N1, N2), index i <-> frequency i - N/2.
+    ``x``: (M, 3) real.  Returns complex128 (M,).
+    """
+    fhat = np.ascontiguousarray(fhat, dtype=np.complex128)
+    N = _shape3(fhat.shape)
+    x = _points(x)
+    f = np.zeros(x.shape[0], dtype=np.complex128)
+    rc = _load().oracle_ndft_trafo(N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   _dptr(fhat.view(np.float64)), x.shape[0], _dptr(x),
+                                   _dptr(f.view(np.float64)), threads or default_threads())
+    if rc:
+        raise RuntimeError(f"oracle_ndft_trafo failed ({rc})")
+    return f
+
+
+def ndft_adjoint(f: np.ndarray, x: np.ndarray, N, threads: int | None = None) -> np.ndarray:
+    """fhat_k = sum_j f_j exp(+2 pi i k.x_j): the conjugate transpose of ``ndft_trafo``."""
+    N = _shape3(N)
+    x = _points(x)
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.complex128).reshape(-1))
+    if f.shape[0] != x.shape[0]:
+        raise ValueError("f and x disagree on M")
+    out = np.zeros(tuple(N.tolist()), dtype=np.complex128)
+    rc = _load().oracle_ndft_adjoint(N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     x.shape[0], _dptr(x), _dptr(f.view(np.float64)),
+                                     _dptr(out.view(np.float64)), threads or default_threads())
+    if rc:
+        raise RuntimeError(f"oracle_ndft_adjoint failed ({rc})")
+    return out
+
+
+def ndft_grad(fhat: np.ndarray, x: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """df_j/dx_{j,d} = sum_k (-2 pi i k_d) fhat_k exp(-2 pi i k.x_j), shape (M, 3) complex.
+
+    The multiplier is eq. (Lambda) on the unit period in the NFFT sign.
+    """
+    fhat = np.ascontiguousarray(fhat, dtype=np.complex128)
+    N = _shape3(fhat.shape)
+    x = _points(x)
+    out = np.zeros((x.shape[0], 3), dtype=np.complex128)
+    rc = _load().oracle_ndft_grad(N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  _dptr(fhat.view(np.float64)), x.shape[0], _dptr(x),
+                                  _dptr(out.view(np.float64)), threads or default_threads())
+    if rc:
+        raise RuntimeError(f"oracle_ndft_grad failed ({rc})")
+    return out
+
+
+def frequencies(Nd: int) -> np.ndarray:
+    """Frequencies of array indices 0..Nd-1 along one axis: -Nd/2 .. Nd/2-1."""
+    return np.arange(Nd) - Nd // 2
+
+
+def rel_errors(got: np.ndarray, ref: np.ndarray) -> tuple[float, float]:
+    """(rel-l2, rel-linf) = (||got-ref||_2/||ref||_2, max|got-ref| / max|ref|)."""
+    got = np.asarray(got).reshape(-1)
+    ref = np.asarray(ref).reshape(-1)
+    d = got - ref
+    n2 = np.linalg.norm(ref)
+    ninf = np.max(np.abs(ref)) if ref.size else 0.0
+    l2 = float(np.linalg.norm(d) / n2) if n2 > 0 else float(np.linalg.norm(d))
+    li = float(np.max(np.abs(d)) / ninf) if ninf > 0 else float(np.max(np.abs(d), initial=0.0))
+    return l2, li
