@@ -1,0 +1,182 @@
+/*
+ * nfft3.h -- C ABI of the MI355X (gfx950) three-dimensional nonequispaced FFT.
+ *
+ * The library evaluates the truncated Fourier series of Sec. 2.2.1 of
+ * Caliari & Zuccher, "INFFTM: Fast evaluation of 3d Fourier series in MATLAB
+ * with an application to quantum vortex reconnections" (arXiv:1605.01244),
+ * in the NFFT form the paper hands to the NFFT library:
+ *
+ *     f_j = sum_{k in I_N} fhat_k exp(-2 pi i k . x_j),   j = 0 .. M-1,
+ *     I_N = prod_d {-N_d/2, ..., N_d/2 - 1},  N_d even  (Sec. 2, set I_N),
+ *
+ * at points x_j in [-1/2, 1/2)^3 (any finite x is folded periodically).
+ * The result is the windowed approximation of the NFFT literature the paper
+ * cites (Kaiser-Bessel window of half-width m cells on the grid n_d = sigma N_d):
+ * (a) deconvolution by the window transform and zero-padding, (b) a 3-D FFT
+ * of size n, (c) a window sum over the (2m)^3 nearest grid points.  The error
+ * falls like exp(-2 pi m sqrt(1 - 1/sigma)) (the M |log eps|^3 term of the
+ * cost quoted in Sec. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named *_dev are DEVICE pointers (HBM of the GPU the plan lives
+ *    on); pointers without the suffix are host pointers.
+ *  - Complex data are interleaved (re, im) pairs of float (NFFT3_C64) or
+ *    double (NFFT3_C128), i.e. the layout of torch.complex64 / complex128.
+ *  - Coefficients are a C-order (N0, N1, N2) array, the last axis contiguous;
+ *    array index i_d corresponds to frequency k_d = i_d - N_d/2.  (The paper
+ *    stores the same array column-major in MATLAB with index k_d - 1 - N_d/2;
+ *    here axis d of the array is paired with column d of the points.)
+ *  - Points are an (M, 3) row-major FP64 array in both precisions.
+ *  - The plan owns every buffer it allocates (grid, tables, sorted points,
+ *    bins); the caller owns the arrays it passes and must keep them alive
+ *    until the work enqueued on the plan's stream has finished.
+ *  - All work is enqueued on the plan's HIP stream.  nfft3_trafo,
+ *    nfft3_adjoint, nfft3_grad_points and the stage calls never synchronise
+ *    the host; nfft3_set_points synchronises once (to report non-finite
+ *    points and to size the launches).
+ *  - Every call returns an int status (NFFT3_OK = 0 or a negative code);
+ *    nothing is thrown across the ABI and nothing calls exit().  After
+ *    NFFT3_ERR_HIP, nfft3_last_hip_error() describes the runtime failure.
+ *  - A plan is bound to one stream and is not thread-safe.
+ */
+#ifndef NFFT3_H
+#define NFFT3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nfft3_plan_s *nfft3_plan_t;
+
+/* Precision of coefficients, grid, FFT and window sums.  Point coordinates,
+ * their fold into [-1/2, 1/2) and the split into grid cell + fraction are
+ * always FP64. */
+enum nfft3_dtype { NFFT3_C64 = 0, NFFT3_C128 = 1 };
+
+enum nfft3_status {
+    NFFT3_OK = 0,
+    NFFT3_ERR_INVALID_ARG = -1, /* bad size, sigma, m or count (see nfft3_plan) */
+    NFFT3_ERR_DTYPE = -2,       /* dtype not NFFT3_C64 / NFFT3_C128, or plans mixed */
+    NFFT3_ERR_OOM = -3,         /* device allocation failed                      */
+    NFFT3_ERR_NO_POINTS = -4,   /* trafo/adjoint/grad before nfft3_set_points    */
+    NFFT3_ERR_NONFINITE = -5,   /* a point coordinate is NaN or infinite         */
+    NFFT3_ERR_HIP = -6,         /* HIP runtime error (see nfft3_last_hip_error)  */
+    NFFT3_ERR_NULL = -7,        /* NULL plan or NULL required pointer            */
+    NFFT3_ERR_TIMEOUT = -8      /* batched launch: a stage wait hit its spin limit */
+};
+
+/* Create a plan for coefficient sizes N[0..2] (host array).
+ *   N_d    even, 2 <= N_d (the set I_N of Sec. 2 needs N_d even).
+ *   sigma  oversampling factor > 1; n_d = sigma * N_d must be an even integer
+ *          whose prime factors are 2, 3 and 5, with n_d <= 2048.
+ *   m      window half-width in oversampled cells, 1 <= m <= 10, 2m <= n_d.
+ *          Typical: m = 4 (about 1e-7 relative error at sigma = 2),
+ *          m = 6 (1e-11), m = 8 (1e-14).
+ *   dtype  NFFT3_C64 or NFFT3_C128.
+ *   stream hipStream_t to enqueue on (NULL = the default stream).
+ * Arguments are validated on the host before any HIP call; invalid ones give
+ * NFFT3_ERR_INVALID_ARG / NFFT3_ERR_DTYPE / NFFT3_ERR_NULL and *out = NULL.
+ * Allocates the n0 n1 n2 complex grid and the window tables on the current
+ * device. */
+int nfft3_plan(nfft3_plan_t *out, const int64_t N[3], double sigma, int m, int dtype,
+               void *stream);
+
+/* Rebind the plan to another stream of the same device. */
+int nfft3_set_stream(nfft3_plan_t p, void *stream);
+
+/* Set the M points, x_dev = (M, 3) FP64 device array.  Folds them into
+ * [-1/2, 1/2) (Euclidean remainder, as the mod of Sec. 2.2.1), splits
+ * n_d x into cell and fraction in FP64, bins and sorts them on the device
+ * (counting sort by grid tile) and keeps the sorted copy; x_dev is not
+ * referenced afterwards.  M = 0 is allowed (trafo then writes nothing).
+ * Returns NFFT3_ERR_NONFINITE (and leaves the plan without points) if any
+ * coordinate is NaN or infinite. */
+int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x_dev);
+
+/* Type-2 transform (the evaluation of Sec. 2.2.1):
+ * f_dev[j] ~ sum_k fhat_k exp(-2 pi i k.x_j), j in the caller's point order.
+ * fhat_dev: N0*N1*N2 complex, f_dev: M complex (dtype of the plan).
+ * Uses the plan's grid as workspace. */
+int nfft3_trafo(nfft3_plan_t p, const void *fhat_dev, void *f_dev);
+
+/* Adjoint (type-1) transform, the conjugate transpose of nfft3_trafo's
+ * discrete operator: fhat_dev[k] = sum_j f_j exp(+2 pi i k.x_j) (windowed).
+ * The paper only evaluates series; this is the map a gradient with respect
+ * to the coefficients needs. */
+int nfft3_adjoint(nfft3_plan_t p, const void *f_dev, void *fhat_dev);
+
+/* Gradient with respect to the points for a real loss L(f):
+ *   grad_x_dev[j, d] = Re( conj(G_j) * d f_j / d x_{j,d} ),
+ *   d f_j / d x_{j,d} = sum_k (-2 pi i k_d) fhat_k exp(-2 pi i k.x_j)
+ * (the derivative multipliers of eq. (Lambda) on the unit period), computed
+ * through the window derivative.  G_dev holds dL/dRe f + i dL/dIm f (M
+ * complex, plan dtype); grad_x_dev is (M, 3) FP64.  Recomputes the grid from
+ * fhat_dev. */
+int nfft3_grad_points(nfft3_plan_t p, const void *fhat_dev, const void *G_dev, double *grad_x_dev);
+
+/* Evaluate the coefficient field and, for each bit d set in deriv_mask
+ * (bit 0,1,2 = axis 0,1,2), the derivative field sum_k (-2 pi i k_d) fhat_k
+ * exp(-2 pi i k.x) at the plan's points.  out_dev holds (1 + popcount(mask))
+ * consecutive blocks of M complex values: the field first, then the
+ * derivative fields in axis order. */
+int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int deriv_mask);
+
+/* Batched type-2 evaluation of T independent plans (own N, own points, same
+ * dtype, sigma and m) in ONE persistent kernel launch.  For plan t,
+ * fhat_dev[t] holds its coefficients and out_dev[t] receives
+ * (1 + popcount(deriv_mask)) blocks of M_t values as in nfft3_trafo_fields.
+ * fhat_dev / out_dev are host arrays of T device pointers.  Work is enqueued
+ * on plans[0]'s stream.  The plans must be distinct; each keeps one grid per
+ * evaluated field, allocated on its first batched call with a given mask.
+ * Returns NFFT3_ERR_TIMEOUT if a stage wait exceeded the spin limit set by
+ * nfft3_batch_set_spin_limit (every wave still exits; outputs are invalid). */
+int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
+                      void *const *out_dev, int deriv_mask);
+int nfft3_batch_set_spin_limit(int64_t spins);   /* <= 0 restores the default (no practical limit) */
+
+/* Release every buffer of the plan.  NULL is a no-op. */
+int nfft3_destroy(nfft3_plan_t p);
+
+/* Human-readable text for a status code (static storage). */
+const char *nfft3_strerror(int code);
+/* Text of the last HIP error seen by the library on this thread. */
+const char *nfft3_last_hip_error(void);
+
+/* ---- Introspection and stage access (diagnostics, tests, benchmarks) ---- */
+
+/* n_out[3] = oversampled grid sizes; *M_out = points set (0 if none). */
+int nfft3_get_info(nfft3_plan_t p, int64_t n_out[3], int64_t *M_out);
+
+/* Stage (a)+(b): deconvolve fhat_dev (times -2 pi i k_d when deriv_axis is
+ * 0, 1 or 2; plain when -1), zero-pad and FFT into the plan's grid. */
+int nfft3_stage_grid(nfft3_plan_t p, const void *fhat_dev, int deriv_axis);
+/* Stage (c): window sum of the plan's current grid at the points -> f_dev. */
+int nfft3_stage_interp(nfft3_plan_t p, void *f_dev);
+/* Adjoint stage (c^T): spread f_dev onto the plan's (zeroed) grid. */
+int nfft3_stage_spread(nfft3_plan_t p, const void *f_dev);
+/* Copy the plan's grid (n0 n1 n2 complex, C order, index l_d in [0, n_d))
+ * to dst_dev (to_plan = 0) or from src into the plan (to_plan = 1). */
+int nfft3_grid_copy(nfft3_plan_t p, void *buf_dev, int to_plan);
+
+/* ---- Host-only helpers (no GPU needed) --------------------------------- */
+
+/* Deconvolution factors of one axis: c[i] = phi(0) / I0(m sqrt(b^2 - (2 pi k/n)^2)),
+ * k = i - Nd/2, b = pi (2 - 1/sigma); the factor that multiplies fhat_k before
+ * the FFT when the window is normalised to phi(0) = 1.  c: Nd doubles. */
+int nfft3_deconv_factors(int64_t Nd, double sigma, int m, double *c);
+
+/* Window polynomials used on the device.  For stencil offset index
+ * r = 0 .. 2m-1 (grid index u + r - m + 1 for a point in cell u with
+ * fraction f in [0,1)), the normalised window phi(f - (r - m + 1)) / phi(0)
+ * is sum_q coef[r*(deg+1) + q] * y^q with y = 2f - 1.  Writes the degree to
+ * *deg (capacity: 2m*(cap_deg+1) doubles at coef) for the target accuracy of
+ * dtype. */
+int nfft3_window_poly(int m, double sigma, int dtype, int cap_deg, double *coef, int *deg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NFFT3_H */

@@ -1,0 +1,250 @@
+"""MI355X (gfx950) nonequispaced FFT in three dimensions.
+
+Python binding of ``libnfft3.so`` (C ABI in ``include/nfft3.h``).  This
+module only marshals arguments: every step of the computation -- point
+binning, deconvolution, FFT, window sums, adjoint spreading, point
+gradients -- runs in the library's HIP kernels.  PyTorch provides device
+memory and the current HIP stream; there is no CPU path.
+
+    plan = Plan((256, 256, 256), sigma=2.0, m=4, dtype=torch.complex64)
+    plan.set_points(x)               # (M, 3) float64 on the GPU
+    f = plan.trafo(fhat)             # f_j = sum_k fhat_k exp(-2 pi i k.x_j)
+    fhat_adj = plan.adjoint(f)       # sum_j f_j exp(+2 pi i k.x_j)
+    f = type2(fhat, x, plan)         # differentiable in fhat and x
+
+The evaluated sum is the NFFT problem of Sec. 2.2.1 of Caliari & Zuccher
+(arXiv:1605.01244): frequencies k_d = -N_d/2 .. N_d/2-1 stored at array index
+k_d + N_d/2 (C order), points in the unit box [-1/2, 1/2)^3 (folded
+periodically).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+from ._lib import NFFT3_C64, NFFT3_C128, NFFT3Error, check, lib
+
+__all__ = ["Plan", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error",
+           "set_batch_spin_limit"]
+
+_DT = {torch.complex64: NFFT3_C64, torch.complex128: NFFT3_C128}
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A 3-D NFFT plan: coefficient sizes N, oversampling sigma, window
+    half-width m, precision dtype (torch.complex64 or torch.complex128)."""
+
+    def __init__(self, N: Sequence[int], sigma: float = 2.0, m: int = 8,
+                 dtype: torch.dtype = torch.complex128, device=None):
+        if dtype not in _DT:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("Plan needs a GPU device")
+        self.N = tuple(int(v) for v in N)
+        self.sigma = float(sigma)
+        self.m = int(m)
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        Narr = (ctypes.c_int64 * 3)(*self.N)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(lib.nfft3_plan(ctypes.byref(self._h), Narr, self.sigma, self.m, _DT[dtype],
+                                 ctypes.c_void_p(stream)), "nfft3_plan")
+        n = (ctypes.c_int64 * 3)()
+        check(lib.nfft3_get_info(self._h, n, None), "nfft3_get_info")
+        self.n = tuple(int(v) for v in n)
+        self.M = 0
+        self.epoch = 0
+
+    # -- helpers -------------------------------------------------------
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib.nfft3_set_stream(self._h, ctypes.c_void_p(s)), "nfft3_set_stream")
+
+    def _coeffs(self, fhat: torch.Tensor) -> torch.Tensor:
+        if fhat.shape != self.N:
+            raise ValueError(f"coefficients must have shape {self.N}, got {tuple(fhat.shape)}")
+        if fhat.dtype != self.dtype or fhat.device != self.device:
+            raise TypeError(f"coefficients must be {self.dtype} on {self.device}")
+        return fhat.contiguous()
+
+    def _values(self, f: torch.Tensor, count: int = 1) -> torch.Tensor:
+        if f.dtype != self.dtype or f.device != self.device:
+            raise TypeError(f"values must be {self.dtype} on {self.device}")
+        if f.numel() != count * self.M:
+            raise ValueError(f"expected {count * self.M} values, got {f.numel()}")
+        return f.contiguous()
+
+    def close(self):
+        if self._h:
+            lib.nfft3_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI ---------------------------------------------------------
+    def set_points(self, x: torch.Tensor) -> None:
+        """x: (M, 3) float64 on the plan's device."""
+        if x.dim() != 2 or x.shape[1] != 3:
+            raise ValueError("points must have shape (M, 3)")
+        if x.dtype != torch.float64 or x.device != self.device:
+            raise TypeError("points must be float64 on the plan's device")
+        x = x.contiguous()
+        self._bind_stream()
+        check(lib.nfft3_set_points(self._h, x.shape[0], _ptr(x)), "nfft3_set_points")
+        self.M = int(x.shape[0])
+        self.epoch += 1
+
+    def trafo(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        fhat = self._coeffs(fhat)
+        if out is None:
+            out = torch.empty(self.M, dtype=self.dtype, device=self.device)
+        self._values(out)
+        self._bind_stream()
+        check(lib.nfft3_trafo(self._h, _ptr(fhat), _ptr(out)), "nfft3_trafo")
+        return out
+
+    def trafo_fields(self, fhat: torch.Tensor, deriv_mask: int = 7) -> torch.Tensor:
+        """(1 + popcount(mask), M): the field and its derivative fields."""
+        fhat = self._coeffs(fhat)
+        k = 1 + bin(deriv_mask & 7).count("1")
+        out = torch.empty((k, self.M), dtype=self.dtype, device=self.device)
+        self._bind_stream()
+        check(lib.nfft3_trafo_fields(self._h, _ptr(fhat), _ptr(out), int(deriv_mask)), "nfft3_trafo_fields")
+        return out
+
+    def adjoint(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        f = self._values(f)
+        if out is None:
+            out = torch.empty(self.N, dtype=self.dtype, device=self.device)
+        self._coeffs(out)
+        self._bind_stream()
+        check(lib.nfft3_adjoint(self._h, _ptr(f), _ptr(out)), "nfft3_adjoint")
+        return out
+
+    def grad_points(self, fhat: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
+        """(M, 3) float64: Re(conj(G_j) d f_j / d x_{j,d})."""
+        fhat = self._coeffs(fhat)
+        G = self._values(G)
+        out = torch.empty((self.M, 3), dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        check(lib.nfft3_grad_points(self._h, _ptr(fhat), _ptr(G), _ptr(out)), "nfft3_grad_points")
+        return out
+
+    # -- stage access (tests, benchmarks) ------------------------------------
+    def stage_grid(self, fhat: torch.Tensor, deriv_axis: int = -1) -> None:
+        fhat = self._coeffs(fhat)
+        self._bind_stream()
+        check(lib.nfft3_stage_grid(self._h, _ptr(fhat), int(deriv_axis)), "nfft3_stage_grid")
+
+    def stage_interp(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.M, dtype=self.dtype, device=self.device)
+        self._values(out)
+        self._bind_stream()
+        check(lib.nfft3_stage_interp(self._h, _ptr(out)), "nfft3_stage_interp")
+        return out
+
+    def stage_spread(self, f: torch.Tensor) -> None:
+        f = self._values(f)
+        self._bind_stream()
+        check(lib.nfft3_stage_spread(self._h, _ptr(f)), "nfft3_stage_spread")
+
+    def grid(self) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=self.dtype, device=self.device)
+        self._bind_stream()
+        check(lib.nfft3_grid_copy(self._h, _ptr(out), 0), "nfft3_grid_copy")
+        return out
+
+    def load_grid(self, g: torch.Tensor) -> None:
+        if tuple(g.shape) != self.n or g.dtype != self.dtype or g.device != self.device:
+            raise ValueError("grid must match the plan's oversampled size, dtype and device")
+        g = g.contiguous()
+        self._bind_stream()
+        check(lib.nfft3_grid_copy(self._h, _ptr(g), 1), "nfft3_grid_copy")
+
+
+def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0):
+    """Evaluate every plan's coefficients (and derivative fields) in one
+    batched launch.  Returns a list of (1 + popcount(mask), M_t) tensors."""
+    T = len(plans)
+    if T != len(fhats):
+        raise ValueError("one coefficient array per plan")
+    k = 1 + bin(deriv_mask & 7).count("1")
+    fh = [p._coeffs(f) for p, f in zip(plans, fhats)]
+    outs = [torch.empty((k, p.M), dtype=p.dtype, device=p.device) for p in plans]
+    if T == 0:
+        return outs
+    plans[0]._bind_stream()
+    H = (ctypes.c_void_p * T)(*[p._h.value for p in plans])
+    F = (ctypes.c_void_p * T)(*[f.data_ptr() for f in fh])
+    O = (ctypes.c_void_p * T)(*[o.data_ptr() for o in outs])
+    check(lib.nfft3_batch_trafo(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo")
+    return outs
+
+
+def set_batch_spin_limit(spins: int) -> None:
+    check(lib.nfft3_batch_set_spin_limit(int(spins)), "nfft3_batch_set_spin_limit")
+
+
+class _Type2(torch.autograd.Function):
+    """f = A(x) fhat.  Backward: grad_fhat = A^H G (adjoint spreading),
+    grad_x[j, d] = Re(conj(G_j) d f_j/d x_{j,d}) (window derivative)."""
+
+    @staticmethod
+    def forward(ctx, fhat, x, plan):
+        plan.set_points(x.detach())
+        ctx.plan = plan
+        ctx.epoch = plan.epoch
+        ctx.save_for_backward(fhat, x)
+        return plan.trafo(fhat.detach())
+
+    @staticmethod
+    def backward(ctx, G):
+        fhat, x = ctx.saved_tensors
+        plan = ctx.plan
+        if plan.epoch != ctx.epoch:      # points were replaced since forward
+            plan.set_points(x.detach())
+            ctx.epoch = plan.epoch
+        G = G.contiguous()
+        gf = plan.adjoint(G) if ctx.needs_input_grad[0] else None
+        gx = plan.grad_points(fhat.detach(), G) if ctx.needs_input_grad[1] else None
+        return gf, gx, None
+
+
+def type2(fhat: torch.Tensor, x: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable type-2 NFFT: f_j = sum_k fhat_k exp(-2 pi i k.x_j)."""
+    return _Type2.apply(fhat, x, plan)
+
+
+# -- host-only helpers (no GPU needed) ----------------------------------------
+
+def deconv_factors(Nd: int, sigma: float, m: int):
+    import numpy as np
+    out = np.zeros(int(Nd), dtype=np.float64)
+    check(lib.nfft3_deconv_factors(int(Nd), float(sigma), int(m),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "nfft3_deconv_factors")
+    return out
+
+
+def window_poly(m: int, sigma: float, dtype: torch.dtype = torch.complex128, cap_deg: int = 24):
+    """(2m, deg+1) monomial coefficients in y = 2f - 1 of the window pieces."""
+    import numpy as np
+    buf = np.zeros(2 * int(m) * (cap_deg + 1), dtype=np.float64)
+    deg = ctypes.c_int(0)
+    check(lib.nfft3_window_poly(int(m), float(sigma), _DT[dtype], int(cap_deg),
+                                buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(deg)),
+          "nfft3_window_poly")
+    d = deg.value
+    return buf[: 2 * int(m) * (d + 1)].reshape(2 * int(m), d + 1)

@@ -1,0 +1,485 @@
+// C ABI of libnfft3: argument validation, plan construction, host-side
+// tables (deconvolution factors, window polynomials, FFT twiddles) and the
+// orchestration of the device stages.  See include/nfft3.h for the contract.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <new>
+
+#include "internal.h"
+
+namespace nfft3 {
+
+static thread_local std::string g_last_hip;
+
+void set_hip_error(hipError_t e, const char *where) {
+    g_last_hip = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+}
+
+void allow_lds(const void *kernel, size_t bytes) {
+    if (bytes > 65536) hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Host tables
+// ---------------------------------------------------------------------------
+
+// Modified Bessel function I0 by its power series sum_q (x^2/4)^q / (q!)^2,
+// summed in long double (all terms positive, no cancellation).
+static long double i0_series(long double x) {
+    const long double y = x * x / 4.0L;
+    long double term = 1.0L, sum = 1.0L;
+    for (int q = 1; q < 500; ++q) {
+        term *= y / ((long double)q * (long double)q);
+        sum += term;
+        if (term < sum * 1e-21L) break;
+    }
+    return sum;
+}
+
+double bessel_i0(double x) { return (double)i0_series((long double)x); }
+
+// Normalised Kaiser-Bessel window phi(t)/phi(0), |t| <= m, in the form
+// (m/s) e^{b(s-m)} expm1(-2bs)/expm1(-2bm), s = sqrt(m^2 - t^2), which has no
+// overflow for any m and no cancellation as s -> 0.
+static long double kb_norm(long double t, int m, long double b) {
+    long double at = fabsl(t);
+    if (at > (long double)m) return 0.0L;
+    long double s2 = ((long double)m - at) * ((long double)m + at);
+    long double den = expm1l(-2.0L * b * m);
+    if (s2 <= 0.0L) return (long double)m * expl(-b * m) * (2.0L * b) / (-den);
+    long double s = sqrtl(s2);
+    return ((long double)m / s) * expl(b * (s - m)) * (expm1l(-2.0L * b * s) / den);
+}
+
+// c[i] = phi(0) / I0(m sqrt(b^2 - (2 pi k / n)^2)), k = i - Nd/2, with
+// phi(0) = sinh(b m)/(pi m): the reciprocal of n phihat(k) for the window
+// normalised to phi(0) = 1.
+void deconv_factors(int64_t Nd, int64_t nd, int m, double b, double *c) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    const long double phi0 = sinhl((long double)b * m) / (pi * m);
+    for (int64_t i = 0; i < Nd; ++i) {
+        long double k = (long double)(i - Nd / 2);
+        long double w = 2.0L * pi * k / (long double)nd;
+        long double arg = (long double)b * b - w * w;
+        long double i0 = i0_series((long double)m * sqrtl(arg > 0 ? arg : 0));
+        c[i] = (double)(phi0 / i0);
+    }
+}
+
+// Chebyshev interpolation of each window piece on [0,1] (variable y = 2f-1),
+// converted to monomials in y.  Picks the smallest degree whose error on a
+// fine sample is below tol (relative to phi(0) = 1).  Returns the degree, or
+// -1 if cap_deg is not enough.
+int window_poly(int m, double b, double tol, int cap_deg, std::vector<double> &coef) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    const int R = 2 * m;
+    for (int deg = 2; deg <= cap_deg; ++deg) {
+        const int K = deg + 1;
+        std::vector<long double> mono((size_t)R * K, 0.0L);
+        for (int r = 0; r < R; ++r) {
+            const int off = r - m + 1;
+            // Chebyshev coefficients from values at the K Chebyshev nodes
+            std::vector<long double> fv(K), ck(K, 0.0L);
+            for (int i = 0; i < K; ++i) {
+                long double y = cosl(pi * (i + 0.5L) / K);
+                fv[i] = kb_norm((y + 1.0L) / 2.0L - off, m, b);
+            }
+            for (int k = 0; k < K; ++k) {
+                long double s = 0.0L;
+                for (int i = 0; i < K; ++i) s += fv[i] * cosl(pi * k * (i + 0.5L) / K);
+                ck[k] = (k == 0 ? 1.0L : 2.0L) * s / K;
+            }
+            // monomial coefficients: accumulate c_k T_k(y) with T recurrence
+            std::vector<long double> tkm(K, 0.0L), tk(K, 0.0L), tkp(K, 0.0L);
+            tkm[0] = 1.0L;                 // T0
+            if (K > 1) tk[1] = 1.0L;       // T1
+            for (int j = 0; j < K; ++j) mono[(size_t)r * K + j] += ck[0] * tkm[j];
+            if (K > 1)
+                for (int j = 0; j < K; ++j) mono[(size_t)r * K + j] += ck[1] * tk[j];
+            for (int k = 2; k < K; ++k) {
+                for (int j = 0; j < K; ++j) tkp[j] = -tkm[j] + (j > 0 ? 2.0L * tk[j - 1] : 0.0L);
+                for (int j = 0; j < K; ++j) mono[(size_t)r * K + j] += ck[k] * tkp[j];
+                tkm.swap(tk);
+                tk.swap(tkp);
+            }
+        }
+        // check in double Horner (the device evaluates the same way)
+        double err = 0.0;
+        for (int r = 0; r < R && err <= tol; ++r) {
+            const int off = r - m + 1;
+            for (int s = 0; s <= 400; ++s) {
+                double f = s / 400.0;
+                double y = 2.0 * f - 1.0;
+                double p = (double)mono[(size_t)r * K + deg];
+                for (int q = deg - 1; q >= 0; --q) p = p * y + (double)mono[(size_t)r * K + q];
+                double ex = (double)kb_norm((long double)f - off, m, b);
+                err = std::max(err, fabs(p - ex));
+            }
+        }
+        if (err <= tol) {
+            coef.assign((size_t)R * K, 0.0);
+            for (size_t i = 0; i < coef.size(); ++i) coef[i] = (double)mono[i];
+            return deg;
+        }
+    }
+    return -1;
+}
+
+// Radices 8, 4, 2, 3, 5 whose product is n (largest first).
+bool factor_radices(int n, std::vector<int> &rad) {
+    rad.clear();
+    int a = 0;
+    while (n % 2 == 0) { n /= 2; ++a; }
+    int q = a / 3, r = a % 3;
+    if (r == 1 && q > 0) { q -= 1; r = 4; }
+    for (int i = 0; i < q; ++i) rad.push_back(8);
+    if (r == 4) { rad.push_back(4); rad.push_back(4); }
+    else if (r == 2) rad.push_back(4);
+    else if (r == 1) rad.push_back(2);
+    while (n % 3 == 0) { n /= 3; rad.push_back(3); }
+    while (n % 5 == 0) { n /= 5; rad.push_back(5); }
+    return n == 1 && rad.size() <= 16;
+}
+
+// ---------------------------------------------------------------------------
+// Plan lifetime
+// ---------------------------------------------------------------------------
+
+static void free_points(nfft3_plan_impl *p) {
+    hipFree(p->xs); p->xs = nullptr;
+    hipFree(p->perm); p->perm = nullptr;
+    hipFree(p->bin_of); p->bin_of = nullptr;
+    hipFree(p->rank); p->rank = nullptr;
+    p->cap_pts = 0;
+}
+
+static void free_plan(nfft3_plan_impl *p) {
+    if (!p) return;
+    hipFree(p->grid);
+    for (void *g : p->extra_grids) hipFree(g);
+    for (int d = 0; d < 3; ++d) { hipFree(p->cdec[d]); hipFree(p->fft[d].tw); }
+    hipFree(p->wcoef);
+    free_points(p);
+    hipFree(p->flag);
+    hipFree(p->bins.counts);
+    hipFree(p->bins.offsets);
+    hipFree(p->sub.items);
+}
+
+static int validate(const int64_t N[3], double sigma, int m, int dtype, int64_t n[3]) {
+    if (dtype != NFFT3_C64 && dtype != NFFT3_C128) return NFFT3_ERR_DTYPE;
+    if (!(sigma > 1.0) || !isfinite(sigma)) return NFFT3_ERR_INVALID_ARG;
+    if (m < 1 || m > 10) return NFFT3_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d) {
+        if (N[d] < 2 || (N[d] % 2) != 0 || N[d] > 4096) return NFFT3_ERR_INVALID_ARG;
+        double nd = sigma * (double)N[d];
+        int64_t ni = (int64_t)llround(nd);
+        if (fabs(nd - (double)ni) > 1e-9 * nd) return NFFT3_ERR_INVALID_ARG;
+        if (ni % 2 != 0 || ni > 2048 || ni < 2 * m) return NFFT3_ERR_INVALID_ARG;
+        std::vector<int> rad;
+        if (!factor_radices((int)ni, rad)) return NFFT3_ERR_INVALID_ARG;
+        n[d] = ni;
+    }
+    return NFFT3_OK;
+}
+
+template <typename T>
+static int upload_real(const std::vector<double> &v, void **dst) {
+    std::vector<T> h(v.begin(), v.end());
+    NFFT3_HIP_TRY(hipMalloc(dst, sizeof(T) * std::max<size_t>(h.size(), 1)));
+    NFFT3_HIP_TRY(hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return NFFT3_OK;
+}
+
+template <typename T>
+static int upload_twiddles(int n, void **dst) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    std::vector<T> h(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+        // exp(-2 pi i k/n), angle reduced to the first octant by symmetry-free
+        // long double evaluation (error ~1e-19, below either precision)
+        long double a = -2.0L * pi * (long double)k / (long double)n;
+        h[2 * k] = (T)cosl(a);
+        h[2 * k + 1] = (T)sinl(a);
+    }
+    // exact values at the quarter points
+    for (int k = 0; k < n; ++k) {
+        if ((4LL * k) % n == 0) {
+            int qd = (int)((4LL * k) / n);
+            const T re[4] = {1, 0, -1, 0}, im[4] = {0, -1, 0, 1};
+            h[2 * k] = re[qd];
+            h[2 * k + 1] = im[qd];
+        }
+    }
+    NFFT3_HIP_TRY(hipMalloc(dst, sizeof(T) * h.size()));
+    NFFT3_HIP_TRY(hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return NFFT3_OK;
+}
+
+static int build_plan(nfft3_plan_impl *p) {
+    const bool f64 = p->dtype == NFFT3_C128;
+    NFFT3_HIP_TRY(hipGetDevice(&p->device));
+    const size_t total = (size_t)p->n[0] * p->n[1] * p->n[2];
+    NFFT3_HIP_TRY(hipMalloc(&p->grid, total * p->elt));
+    NFFT3_HIP_TRY(hipMalloc(&p->flag, 64));
+    for (int d = 0; d < 3; ++d) {
+        std::vector<double> c((size_t)p->N[d]);
+        deconv_factors(p->N[d], p->n[d], p->m, p->b, c.data());
+        int rc = f64 ? upload_real<double>(c, &p->cdec[d]) : upload_real<float>(c, &p->cdec[d]);
+        if (rc) return rc;
+        std::vector<int> rad;
+        factor_radices((int)p->n[d], rad);
+        p->fft[d].n = (int)p->n[d];
+        p->fft[d].nrad = (int)rad.size();
+        for (size_t i = 0; i < rad.size(); ++i) p->fft[d].radix[i] = rad[i];
+        rc = f64 ? upload_twiddles<double>((int)p->n[d], &p->fft[d].tw)
+                 : upload_twiddles<float>((int)p->n[d], &p->fft[d].tw);
+        if (rc) return rc;
+    }
+    std::vector<double> coef;
+    const double tol = f64 ? 4e-16 : 2e-8;
+    int deg = window_poly(p->m, p->b, tol, kMaxDeg, coef);
+    if (deg < 0) deg = window_poly(p->m, p->b, f64 ? 2e-15 : 1e-7, kMaxDeg, coef);
+    if (deg < 0) return NFFT3_ERR_INVALID_ARG;
+    p->deg = deg;
+    int rc = f64 ? upload_real<double>(coef, &p->wcoef) : upload_real<float>(coef, &p->wcoef);
+    if (rc) return rc;
+    // bins: tiles of 8 cells (more for very large grids)
+    int64_t nb = 1;
+    for (int d = 0; d < 3; ++d) {
+        int B = 8;
+        while (p->n[d] / B > 64) B *= 2;
+        if (B > p->n[d]) B = (int)p->n[d];
+        p->bins.B[d] = B;
+        p->bins.nb[d] = (int)((p->n[d] + B - 1) / B);
+        nb *= p->bins.nb[d];
+    }
+    p->bins.nbins = nb;
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nb));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nb + 1)));
+    return NFFT3_OK;
+}
+
+}  // namespace nfft3
+
+using namespace nfft3;
+
+extern "C" {
+
+int nfft3_plan(nfft3_plan_t *out, const int64_t N[3], double sigma, int m, int dtype, void *stream) {
+    if (!out) return NFFT3_ERR_NULL;
+    *out = nullptr;
+    if (!N) return NFFT3_ERR_NULL;
+    int64_t n[3];
+    int rc = validate(N, sigma, m, dtype, n);
+    if (rc) return rc;
+    nfft3_plan_s *p = new (std::nothrow) nfft3_plan_s();
+    if (!p) return NFFT3_ERR_OOM;
+    p->dtype = dtype;
+    p->m = m;
+    p->sigma = sigma;
+    p->b = M_PI * (2.0 - 1.0 / sigma);
+    for (int d = 0; d < 3; ++d) { p->N[d] = N[d]; p->n[d] = n[d]; }
+    p->stream = (hipStream_t)stream;
+    p->elt = dtype == NFFT3_C128 ? 16 : 8;
+    rc = build_plan(p);
+    if (rc) {
+        free_plan(p);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return NFFT3_OK;
+}
+
+int nfft3_set_stream(nfft3_plan_t p, void *stream) {
+    if (!p) return NFFT3_ERR_NULL;
+    p->stream = (hipStream_t)stream;
+    return NFFT3_OK;
+}
+
+int nfft3_destroy(nfft3_plan_t p) {
+    if (!p) return NFFT3_OK;
+    if (p->stream) hipStreamSynchronize(p->stream);
+    free_plan(p);
+    delete p;
+    return NFFT3_OK;
+}
+
+int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (M < 0 || M > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
+    if (M > 0 && !x) return NFFT3_ERR_NULL;
+    p->have_points = false;
+    p->M = 0;
+    if (M > p->cap_pts) {
+        free_points(p);
+        NFFT3_HIP_TRY(hipMalloc(&p->xs, sizeof(double) * 3 * M));
+        NFFT3_HIP_TRY(hipMalloc(&p->perm, sizeof(int) * M));
+        NFFT3_HIP_TRY(hipMalloc(&p->bin_of, sizeof(int) * M));
+        NFFT3_HIP_TRY(hipMalloc(&p->rank, sizeof(int) * M));
+        p->cap_pts = M;
+    }
+    int rc = launch_set_points(p, M, x);
+    if (rc) return rc;
+    NFFT3_HIP_TRY(hipStreamSynchronize(p->stream));
+    int flag = 0;
+    NFFT3_HIP_TRY(hipMemcpy(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag & 1) return NFFT3_ERR_NONFINITE;
+    p->M = M;
+    p->have_points = true;
+    p->epoch += 1;
+    return NFFT3_OK;
+}
+
+int nfft3_trafo(nfft3_plan_t p, const void *fhat, void *f) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!p->have_points) return NFFT3_ERR_NO_POINTS;
+    if (!fhat || (p->M > 0 && !f)) return NFFT3_ERR_NULL;
+    int rc = launch_grid_forward(p, fhat, p->grid, -1);
+    if (rc) return rc;
+    return launch_interp(p, p->grid, f);
+}
+
+int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat, void *out, int mask) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!p->have_points) return NFFT3_ERR_NO_POINTS;
+    if (mask < 0 || mask > 7) return NFFT3_ERR_INVALID_ARG;
+    if (!fhat || (p->M > 0 && !out)) return NFFT3_ERR_NULL;
+    char *o = (char *)out;
+    for (int field = -1; field < 3; ++field) {
+        if (field >= 0 && !(mask & (1 << field))) continue;
+        int rc = launch_grid_forward(p, fhat, p->grid, field);
+        if (rc) return rc;
+        rc = launch_interp(p, p->grid, o);
+        if (rc) return rc;
+        o += (size_t)p->M * p->elt;
+    }
+    return NFFT3_OK;
+}
+
+int nfft3_adjoint(nfft3_plan_t p, const void *f, void *fhat) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!p->have_points) return NFFT3_ERR_NO_POINTS;
+    if (!fhat || (p->M > 0 && !f)) return NFFT3_ERR_NULL;
+    const size_t total = (size_t)p->n[0] * p->n[1] * p->n[2];
+    int rc = launch_zero(p, p->grid, total * p->elt);
+    if (rc) return rc;
+    rc = launch_spread(p, f, p->grid);
+    if (rc) return rc;
+    return launch_grid_adjoint(p, p->grid, fhat);
+}
+
+int nfft3_grad_points(nfft3_plan_t p, const void *fhat, const void *G, double *grad_x) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!p->have_points) return NFFT3_ERR_NO_POINTS;
+    if (!fhat || (p->M > 0 && (!G || !grad_x))) return NFFT3_ERR_NULL;
+    int rc = launch_grid_forward(p, fhat, p->grid, -1);
+    if (rc) return rc;
+    return launch_grad(p, p->grid, G, grad_x);
+}
+
+int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out,
+                      int mask) {
+    if (T < 0 || mask < 0 || mask > 7) return NFFT3_ERR_INVALID_ARG;
+    if (T == 0) return NFFT3_OK;
+    if (!plans || !fhat || !out) return NFFT3_ERR_NULL;
+    for (int t = 0; t < T; ++t) {
+        if (!plans[t] || !fhat[t]) return NFFT3_ERR_NULL;
+        if (!plans[t]->have_points) return NFFT3_ERR_NO_POINTS;
+        if (plans[t]->M > 0 && !out[t]) return NFFT3_ERR_NULL;
+        if (plans[t]->dtype != plans[0]->dtype) return NFFT3_ERR_DTYPE;
+        if (plans[t]->m != plans[0]->m || plans[t]->sigma != plans[0]->sigma) return NFFT3_ERR_INVALID_ARG;
+        for (int u = 0; u < t; ++u)
+            if (plans[u] == plans[t]) return NFFT3_ERR_INVALID_ARG;
+    }
+    std::vector<nfft3_plan_impl *> pl(plans, plans + T);
+    return launch_batch(T, pl.data(), fhat, out, mask);
+}
+
+const char *nfft3_strerror(int code) {
+    switch (code) {
+        case NFFT3_OK: return "ok";
+        case NFFT3_ERR_INVALID_ARG: return "invalid argument";
+        case NFFT3_ERR_DTYPE: return "unsupported or mismatched dtype";
+        case NFFT3_ERR_OOM: return "device out of memory";
+        case NFFT3_ERR_NO_POINTS: return "no points set on the plan";
+        case NFFT3_ERR_NONFINITE: return "non-finite point coordinate";
+        case NFFT3_ERR_HIP: return "HIP runtime error";
+        case NFFT3_ERR_NULL: return "NULL plan or pointer";
+        case NFFT3_ERR_TIMEOUT: return "batched launch: stage wait exceeded the spin limit";
+        default: return "unknown status";
+    }
+}
+
+const char *nfft3_last_hip_error(void) { return g_last_hip.c_str(); }
+
+int nfft3_get_info(nfft3_plan_t p, int64_t n_out[3], int64_t *M_out) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (n_out)
+        for (int d = 0; d < 3; ++d) n_out[d] = p->n[d];
+    if (M_out) *M_out = p->have_points ? p->M : 0;
+    return NFFT3_OK;
+}
+
+int nfft3_stage_grid(nfft3_plan_t p, const void *fhat, int deriv_axis) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!fhat) return NFFT3_ERR_NULL;
+    if (deriv_axis < -1 || deriv_axis > 2) return NFFT3_ERR_INVALID_ARG;
+    return launch_grid_forward(p, fhat, p->grid, deriv_axis);
+}
+
+int nfft3_stage_interp(nfft3_plan_t p, void *f) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!p->have_points) return NFFT3_ERR_NO_POINTS;
+    if (p->M > 0 && !f) return NFFT3_ERR_NULL;
+    return launch_interp(p, p->grid, f);
+}
+
+int nfft3_stage_spread(nfft3_plan_t p, const void *f) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!p->have_points) return NFFT3_ERR_NO_POINTS;
+    if (p->M > 0 && !f) return NFFT3_ERR_NULL;
+    const size_t total = (size_t)p->n[0] * p->n[1] * p->n[2];
+    int rc = launch_zero(p, p->grid, total * p->elt);
+    if (rc) return rc;
+    return launch_spread(p, f, p->grid);
+}
+
+int nfft3_grid_copy(nfft3_plan_t p, void *buf, int to_plan) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!buf) return NFFT3_ERR_NULL;
+    const size_t bytes = (size_t)p->n[0] * p->n[1] * p->n[2] * p->elt;
+    if (to_plan)
+        NFFT3_HIP_TRY(hipMemcpyAsync(p->grid, buf, bytes, hipMemcpyDeviceToDevice, p->stream));
+    else
+        NFFT3_HIP_TRY(hipMemcpyAsync(buf, p->grid, bytes, hipMemcpyDeviceToDevice, p->stream));
+    return NFFT3_OK;
+}
+
+int nfft3_deconv_factors(int64_t Nd, double sigma, int m, double *c) {
+    if (!c) return NFFT3_ERR_NULL;
+    if (Nd < 2 || Nd % 2 || !(sigma > 1.0) || m < 1 || m > 10) return NFFT3_ERR_INVALID_ARG;
+    double nd = sigma * (double)Nd;
+    deconv_factors(Nd, (int64_t)llround(nd), m, M_PI * (2.0 - 1.0 / sigma), c);
+    return NFFT3_OK;
+}
+
+int nfft3_window_poly(int m, double sigma, int dtype, int cap_deg, double *coef, int *deg) {
+    if (!coef || !deg) return NFFT3_ERR_NULL;
+    if (m < 1 || m > 10 || !(sigma > 1.0) || cap_deg < 2) return NFFT3_ERR_INVALID_ARG;
+    if (dtype != NFFT3_C64 && dtype != NFFT3_C128) return NFFT3_ERR_DTYPE;
+    std::vector<double> c;
+    double b = M_PI * (2.0 - 1.0 / sigma);
+    int d = window_poly(m, b, dtype == NFFT3_C128 ? 4e-16 : 2e-8, std::min(cap_deg, kMaxDeg), c);
+    if (d < 0) d = window_poly(m, b, dtype == NFFT3_C128 ? 2e-15 : 1e-7, std::min(cap_deg, kMaxDeg), c);
+    if (d < 0) return NFFT3_ERR_INVALID_ARG;
+    memcpy(coef, c.data(), sizeof(double) * c.size());
+    *deg = d;
+    return NFFT3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,449 @@
+// Stage (a)+(b) of the windowed evaluation: deconvolution, zero-padding and
+// the 3-D FFT on the oversampled grid, and the transposed pipeline for the
+// adjoint.  Each axis is one pass of self-sorting (Stockham) radix-8/4/2/3/5
+// FFTs held in LDS:
+//   * the contiguous axis (2) runs lines = rows, loaded with unit stride;
+//   * the strided axes (1, 0) run tiles of C adjacent columns, so every
+//     global access is a C*elt-byte (128 B) contiguous segment, transposed
+//     into LDS lines of padded stride n+1.
+// Zero-padding is pruned: the forward passes only read the N_d nonzero
+// inputs per line and write into the same grid buffer in place
+//   pass 1 (axis 2): fhat (N0,N1,N2) -> grid[i0][i1][0..n2)   i0<N0, i1<N1
+//   pass 2 (axis 1): grid[i0][0..N1)[x] -> grid[i0][0..n1)[x]  i0<N0
+//   pass 3 (axis 0): grid[0..N0)[y][x] -> grid[0..n0)[y][x]
+// and the adjoint keeps only the N_d outputs per line in reverse order.
+// Compact index i of a pruned line holds frequency i - L/2, which sits at
+// FFT position (i - L/2) mod n.
+#include "internal.h"
+
+namespace nfft3 {
+
+constexpr int kFftThreads = 256;
+constexpr int kMaxStages = 16;
+
+struct RadixList {
+    int nrad;
+    int r[kMaxStages];
+};
+
+// ---------------------------------------------------------------- DFTs ----
+// In-place DFT of R values with kernel exp(sgn 2 pi i / R), sgn = FWD ? -1 : +1.
+template <typename C, bool FWD>
+__device__ __forceinline__ C mul_i(C a) {  // multiply by sgn*i
+    C r;
+    if (FWD) { r.x = a.y; r.y = -a.x; }    // -i * a
+    else { r.x = -a.y; r.y = a.x; }        // +i * a
+    return r;
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void dft2(c_t<T> *v) {
+    c_t<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void dft4(c_t<T> *v) {
+    c_t<T> c0 = cadd(v[0], v[2]), c1 = csub(v[0], v[2]);
+    c_t<T> c2 = cadd(v[1], v[3]), c3 = mul_i<c_t<T>, FWD>(csub(v[1], v[3]));
+    v[0] = cadd(c0, c2);
+    v[2] = csub(c0, c2);
+    v[1] = cadd(c1, c3);
+    v[3] = csub(c1, c3);
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void dft8(c_t<T> *v) {
+    const T h = (T)0.70710678118654752440084436210485;
+    c_t<T> a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { a[r] = cadd(v[r], v[r + 4]); b[r] = csub(v[r], v[r + 4]); }
+    // b_r *= w^r, w = exp(sgn 2 pi i/8)
+    {
+        c_t<T> t = b[1];   // w = h (1 + sgn i)
+        b[1] = FWD ? cmk<T>(h * (t.x + t.y), h * (t.y - t.x)) : cmk<T>(h * (t.x - t.y), h * (t.y + t.x));
+        b[2] = mul_i<c_t<T>, FWD>(b[2]);
+        t = b[3];          // w^3 = h (-1 + sgn i)
+        b[3] = FWD ? cmk<T>(h * (t.y - t.x), -h * (t.x + t.y)) : cmk<T>(-h * (t.x + t.y), h * (t.x - t.y));
+    }
+    dft4<T, FWD>(a);
+    dft4<T, FWD>(b);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { v[2 * r] = a[r]; v[2 * r + 1] = b[r]; }
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void dft3(c_t<T> *v) {
+    const T s3 = (T)0.86602540378443864676372317075294;   // sqrt(3)/2
+    c_t<T> t = cadd(v[1], v[2]);
+    c_t<T> u = mul_i<c_t<T>, FWD>(csub(v[1], v[2]));
+    c_t<T> x0 = v[0];
+    v[0] = cadd(x0, t);
+    c_t<T> a = cmk<T>(x0.x - (T)0.5 * t.x, x0.y - (T)0.5 * t.y);
+    v[1] = cmk<T>(a.x + s3 * u.x, a.y + s3 * u.y);
+    v[2] = cmk<T>(a.x - s3 * u.x, a.y - s3 * u.y);
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void dft5(c_t<T> *v) {
+    // X_k = sum_r x_r w^{rk}, w = exp(sgn 2 pi i/5); real/imag parts of w, w^2
+    const T c1 = (T)0.30901699437494742410229341718282, c2 = (T)-0.80901699437494742410229341718282;
+    const T s1 = (T)0.95105651629515357211643933337938, s2 = (T)0.58778525229247312916870595463907;
+    c_t<T> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    c_t<T> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    c_t<T> x0 = v[0];
+    c_t<T> p1 = cmk<T>(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+    c_t<T> p2 = cmk<T>(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+    // q1 = sgn i (s1 b1 + s2 b2), q2 = sgn i (s2 b1 - s1 b2)
+    c_t<T> q1 = mul_i<c_t<T>, FWD>(cmk<T>(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    c_t<T> q2 = mul_i<c_t<T>, FWD>(cmk<T>(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    v[0] = cadd(x0, cadd(a1, a2));
+    v[1] = cadd(p1, q1);
+    v[4] = csub(p1, q1);
+    v[2] = cadd(p2, q2);
+    v[3] = csub(p2, q2);
+}
+
+template <typename T, int R, bool FWD>
+__device__ __forceinline__ void dft_small(c_t<T> *v) {
+    if constexpr (R == 2) dft2<T, FWD>(v);
+    else if constexpr (R == 3) dft3<T, FWD>(v);
+    else if constexpr (R == 4) dft4<T, FWD>(v);
+    else if constexpr (R == 5) dft5<T, FWD>(v);
+    else dft8<T, FWD>(v);
+}
+
+// ------------------------------------------------------ Stockham stage ----
+// One radix-R stage over `nlines` lines of length n held in LDS (line stride
+// ls).  Butterfly j of a line reads x[j + r n/R], twiddles by
+// W^{r (j mod Ns) n/(Ns R)}, W = exp(-+2 pi i/n), and writes the R results to
+// (j/Ns) Ns R + (j mod Ns) + r Ns.  All reads complete (barrier) before any
+// write, so a single buffer suffices.
+template <typename T, int R, int VMAX, bool FWD>
+__device__ __forceinline__ void stockham_stage(c_t<T> *buf, int ls, int nlines, int n, int Ns,
+                                               const c_t<T> *__restrict__ tw, int tid) {
+    constexpr int BMAX = VMAX / R;
+    const int nbl = n / R;
+    const int NB = nlines * nbl;
+    c_t<T> v[BMAX][R];
+#pragma unroll
+    for (int i = 0; i < BMAX; ++i) {
+        const int bt = tid + i * kFftThreads;
+        if (bt < NB) {
+            const int line = bt / nbl, j = bt - line * nbl;
+            const c_t<T> *src = buf + line * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src[j + r * nbl];
+        }
+    }
+    __syncthreads();
+    const int step = n / (Ns * R);
+#pragma unroll
+    for (int i = 0; i < BMAX; ++i) {
+        const int bt = tid + i * kFftThreads;
+        if (bt < NB) {
+            const int line = bt / nbl, j = bt - line * nbl;
+            const int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c_t<T> w = tw[r * k * step];
+                    v[i][r] = FWD ? cmul(v[i][r], w) : cmulc(v[i][r], w);
+                }
+            }
+            dft_small<T, R, FWD>(v[i]);
+            c_t<T> *dst = buf + line * ls;
+            const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int VMAX, bool FWD>
+__device__ __forceinline__ void stockham_lines(c_t<T> *buf, int ls, int nlines, int n, const RadixList &rl,
+                                               const c_t<T> *__restrict__ tw, int tid) {
+    int Ns = 1;
+    for (int s = 0; s < rl.nrad; ++s) {
+        const int R = rl.r[s];
+        switch (R) {
+            case 8: stockham_stage<T, 8, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
+            case 4: stockham_stage<T, 4, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
+            case 2: stockham_stage<T, 2, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
+            case 3: stockham_stage<T, 3, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
+            default: stockham_stage<T, 5, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
+        }
+        Ns *= R;
+    }
+}
+
+__device__ __forceinline__ int wrap_pos(int i, int L, int n) {
+    int p = i - L / 2;
+    return p < 0 ? p + n : p;
+}
+
+// -------------------------------------------------------- row passes ----
+// MODE 0 (forward, first pass): rows (i0,i1) of fhat, deconvolved by
+//   c0[i0] c1[i1] c2[i2] (times -2 pi i k_d for a derivative field), placed at
+//   wrap_pos(i2) and transformed; all n outputs stored to grid rows (i0,i1).
+// MODE 1 (adjoint, last pass): grid rows (i0,i1), transformed with + sign;
+//   the N2 outputs at wrap_pos(o) times c0 c1 c2 stored to fhat.
+struct RowArgs {
+    const void *in;
+    void *out;
+    const void *c0, *c1, *c2;
+    const void *tw;
+    int n, N0, N1, N2;
+    int64_t grid_s0, grid_s1;   // grid strides of i0, i1 (elements)
+    int lpw;                     // rows per workgroup
+    int deriv;                   // -1 or axis
+    RadixList rl;
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kFftThreads) fft_rows_kernel(RowArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c_t<T> *buf = reinterpret_cast<c_t<T> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int n = a.n;
+    const int ls = n;
+    const int64_t nrows = (int64_t)a.N0 * a.N1;
+    const int64_t row0 = (int64_t)blockIdx.x * a.lpw;
+    const int nl = (int)min<int64_t>(a.lpw, nrows - row0);
+    const T *c0 = (const T *)a.c0, *c1 = (const T *)a.c1, *c2 = (const T *)a.c2;
+    const T twopi = (T)6.283185307179586476925286766559;
+
+    if (MODE == 0) {
+        const c_t<T> *fhat = (const c_t<T> *)a.in;
+        // zero the padded positions, then place the N2 deconvolved inputs
+        for (int idx = tid; idx < nl * n; idx += kFftThreads) buf[idx] = cmk<T>(0, 0);
+        __syncthreads();
+        for (int idx = tid; idx < nl * a.N2; idx += kFftThreads) {
+            const int l = idx / a.N2, i2 = idx - l * a.N2;
+            const int64_t row = row0 + l;
+            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
+            c_t<T> v = fhat[row * a.N2 + i2];
+            T s = c0[i0] * c1[i1] * c2[i2];
+            v.x *= s;
+            v.y *= s;
+            if (a.deriv >= 0) {   // times -2 pi i k_d
+                const int kd = a.deriv == 0 ? i0 - a.N0 / 2 : a.deriv == 1 ? i1 - a.N1 / 2 : i2 - a.N2 / 2;
+                const T f = twopi * (T)kd;
+                v = cmk<T>(f * v.y, -f * v.x);
+            }
+            buf[l * ls + wrap_pos(i2, a.N2, n)] = v;
+        }
+        __syncthreads();
+        stockham_lines<T, 16, true>(buf, ls, nl, n, a.rl, (const c_t<T> *)a.tw, tid);
+        c_t<T> *grid = (c_t<T> *)a.out;
+        for (int idx = tid; idx < nl * n; idx += kFftThreads) {
+            const int l = idx / n, x = idx - l * n;
+            const int64_t row = row0 + l;
+            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
+            grid[i0 * a.grid_s0 + i1 * a.grid_s1 + x] = buf[l * ls + x];
+        }
+    } else {
+        const c_t<T> *grid = (const c_t<T> *)a.in;
+        for (int idx = tid; idx < nl * n; idx += kFftThreads) {
+            const int l = idx / n, x = idx - l * n;
+            const int64_t row = row0 + l;
+            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
+            buf[l * ls + x] = grid[i0 * a.grid_s0 + i1 * a.grid_s1 + x];
+        }
+        __syncthreads();
+        stockham_lines<T, 16, false>(buf, ls, nl, n, a.rl, (const c_t<T> *)a.tw, tid);
+        c_t<T> *fhat = (c_t<T> *)a.out;
+        for (int idx = tid; idx < nl * a.N2; idx += kFftThreads) {
+            const int l = idx / a.N2, o = idx - l * a.N2;
+            const int64_t row = row0 + l;
+            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
+            c_t<T> v = buf[l * ls + wrap_pos(o, a.N2, n)];
+            T s = c0[i0] * c1[i1] * c2[o];
+            v.x *= s;
+            v.y *= s;
+            fhat[row * a.N2 + o] = v;
+        }
+    }
+}
+
+// ----------------------------------------------------- column passes ----
+// In-place transform along a strided axis of tiles of C adjacent columns.
+// Column c of tile (outer, x0) has element i at
+//   data[outer * s_outer + i * s_axis + x0 + c].
+// Input: Lin values (compact, placed at wrap_pos) or all n; output: all n or
+// Lout compact values picked at wrap_pos.
+struct ColArgs {
+    void *data;
+    const void *tw;
+    int n, Lin, Lout;
+    int ncols;          // contiguous extent (columns)
+    int C;              // columns per tile
+    int64_t s_axis, s_outer;
+    RadixList rl;
+};
+
+template <typename T, bool FWD>
+__global__ void __launch_bounds__(kFftThreads) fft_cols_kernel(ColArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c_t<T> *buf = reinterpret_cast<c_t<T> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int n = a.n, C = a.C;
+    const int ls = n + 1;   // padded line stride: columns land in different banks
+    const int x0 = blockIdx.x * C;
+    const int nc = min(C, a.ncols - x0);
+    c_t<T> *data = (c_t<T> *)a.data + (int64_t)blockIdx.y * a.s_outer + x0;
+
+    if (a.Lin < n) {
+        for (int idx = tid; idx < C * ls; idx += kFftThreads) buf[idx] = cmk<T>(0, 0);
+        __syncthreads();
+    }
+    for (int idx = tid; idx < a.Lin * C; idx += kFftThreads) {
+        const int i = idx / C, c = idx - i * C;
+        if (c < nc) {
+            const int pos = a.Lin < n ? wrap_pos(i, a.Lin, n) : i;
+            buf[c * ls + pos] = data[(int64_t)i * a.s_axis + c];
+        }
+    }
+    __syncthreads();
+    stockham_lines<T, 32, FWD>(buf, ls, C, n, a.rl, (const c_t<T> *)a.tw, tid);
+    for (int idx = tid; idx < a.Lout * C; idx += kFftThreads) {
+        const int o = idx / C, c = idx - o * C;
+        if (c < nc) {
+            const int pos = a.Lout < n ? wrap_pos(o, a.Lout, n) : o;
+            data[(int64_t)o * a.s_axis + c] = buf[c * ls + pos];
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers ----
+// Column tiles may use more than 64 KiB of LDS (gfx950 has 160 KiB per CU).
+constexpr size_t kColsLdsMax = 80 * 1024;
+
+static RadixList radix_list(const FftAxisPlan &f) {
+    RadixList rl;
+    rl.nrad = f.nrad;
+    for (int i = 0; i < kMaxStages; ++i) rl.r[i] = i < f.nrad ? f.radix[i] : 0;
+    return rl;
+}
+
+// Largest number of lines such that every stage fits VMAX values per thread.
+static int lines_fit(const FftAxisPlan &f, int vmax, int cap) {
+    int best = 1;
+    for (int L = 1; L <= cap; ++L) {
+        bool ok = true;
+        for (int s = 0; s < f.nrad; ++s) {
+            const int R = f.radix[s];
+            const int NB = L * (f.n / R);
+            const int per = (NB + kFftThreads - 1) / kFftThreads;
+            if (per > vmax / R) { ok = false; break; }
+        }
+        if (ok) best = L;
+        else break;
+    }
+    return best;
+}
+
+template <typename T>
+static int rows_pass(nfft3_plan_impl *p, int mode, const void *in, void *out, int deriv) {
+    const FftAxisPlan &f = p->fft[2];
+    RowArgs a;
+    a.in = in;
+    a.out = out;
+    a.c0 = p->cdec[0];
+    a.c1 = p->cdec[1];
+    a.c2 = p->cdec[2];
+    a.tw = f.tw;
+    a.n = f.n;
+    a.N0 = (int)p->N[0];
+    a.N1 = (int)p->N[1];
+    a.N2 = (int)p->N[2];
+    a.grid_s0 = p->n[1] * p->n[2];
+    a.grid_s1 = p->n[2];
+    a.deriv = deriv;
+    a.rl = radix_list(f);
+    const int cap = std::max(1, (int)(32768 / (f.n * sizeof(c_t<T>))));
+    a.lpw = lines_fit(f, 16, std::max(1, std::min(cap, 64)));
+    const int64_t nrows = p->N[0] * p->N[1];
+    const int64_t nblk = (nrows + a.lpw - 1) / a.lpw;
+    const size_t lds = (size_t)a.lpw * f.n * sizeof(c_t<T>);
+    if (mode == 0)
+        hipLaunchKernelGGL((fft_rows_kernel<T, 0>), dim3((unsigned)nblk), dim3(kFftThreads), lds, p->stream, a);
+    else
+        hipLaunchKernelGGL((fft_rows_kernel<T, 1>), dim3((unsigned)nblk), dim3(kFftThreads), lds, p->stream, a);
+    NFFT3_LAUNCH_CHECK("fft_rows_kernel");
+    return NFFT3_OK;
+}
+
+template <typename T>
+static int cols_pass(nfft3_plan_impl *p, int axis, bool fwd, int Lin, int Lout, int64_t n_outer,
+                     int64_t s_outer) {
+    const FftAxisPlan &f = p->fft[axis];
+    ColArgs a;
+    a.data = p->grid;
+    a.tw = f.tw;
+    a.n = f.n;
+    a.Lin = Lin;
+    a.Lout = Lout;
+    a.ncols = (int)p->n[2];
+    a.s_axis = axis == 0 ? p->n[1] * p->n[2] : p->n[2];
+    a.s_outer = s_outer;
+    a.rl = radix_list(f);
+    // 128-byte column segments, bounded by LDS (64 KiB) and registers
+    int C = (int)(128 / sizeof(c_t<T>));
+    while (C > 1 && (size_t)C * (f.n + 1) * sizeof(c_t<T>) > kColsLdsMax) C /= 2;
+    C = std::min(C, lines_fit(f, 32, C));
+    C = std::min<int>(C, a.ncols);
+    a.C = C;
+    dim3 grid((unsigned)((a.ncols + C - 1) / C), (unsigned)n_outer);
+    const size_t lds = (size_t)C * (f.n + 1) * sizeof(c_t<T>);
+    if (fwd) {
+        allow_lds((const void *)fft_cols_kernel<T, true>, lds);
+        hipLaunchKernelGGL((fft_cols_kernel<T, true>), grid, dim3(kFftThreads), lds, p->stream, a);
+    } else {
+        allow_lds((const void *)fft_cols_kernel<T, false>, lds);
+        hipLaunchKernelGGL((fft_cols_kernel<T, false>), grid, dim3(kFftThreads), lds, p->stream, a);
+    }
+    NFFT3_LAUNCH_CHECK("fft_cols_kernel");
+    return NFFT3_OK;
+}
+
+template <typename T>
+static int grid_forward(nfft3_plan_impl *p, const void *fhat, int deriv) {
+    int rc = rows_pass<T>(p, 0, fhat, p->grid, deriv);
+    if (rc) return rc;
+    // axis 1: tiles over i0 < N0 (outer stride n1 n2)
+    rc = cols_pass<T>(p, 1, true, (int)p->N[1], (int)p->n[1], p->N[0], p->n[1] * p->n[2]);
+    if (rc) return rc;
+    // axis 0: tiles over y < n1 (outer stride n2)
+    return cols_pass<T>(p, 0, true, (int)p->N[0], (int)p->n[0], p->n[1], p->n[2]);
+}
+
+template <typename T>
+static int grid_adjoint(nfft3_plan_impl *p, void *fhat) {
+    int rc = cols_pass<T>(p, 0, false, (int)p->n[0], (int)p->N[0], p->n[1], p->n[2]);
+    if (rc) return rc;
+    rc = cols_pass<T>(p, 1, false, (int)p->n[1], (int)p->N[1], p->N[0], p->n[1] * p->n[2]);
+    if (rc) return rc;
+    return rows_pass<T>(p, 1, p->grid, fhat, -1);
+}
+
+int launch_grid_forward(nfft3_plan_impl *p, const void *fhat, void *grid, int deriv_axis) {
+    void *saved = p->grid;
+    p->grid = grid;
+    int rc = p->dtype == NFFT3_C128 ? grid_forward<double>(p, fhat, deriv_axis)
+                                    : grid_forward<float>(p, fhat, deriv_axis);
+    p->grid = saved;
+    return rc;
+}
+
+int launch_grid_adjoint(nfft3_plan_impl *p, void *grid, void *fhat) {
+    void *saved = p->grid;
+    p->grid = grid;
+    int rc = p->dtype == NFFT3_C128 ? grid_adjoint<double>(p, fhat) : grid_adjoint<float>(p, fhat);
+    p->grid = saved;
+    return rc;
+}
+
+}  // namespace nfft3

@@ -1,0 +1,155 @@
+// Internal declarations shared by the translation units of libnfft3.
+// Device code targets gfx950 (CDNA4): 64-lane wavefronts, 160 KiB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nfft3.h"
+
+namespace nfft3 {
+
+// ----------------------------------------------------------------------------
+// Complex helpers.  Complex values are the HIP vector types float2 / double2
+// (interleaved re, im), so a complex load is one 8- or 16-byte access.
+// ----------------------------------------------------------------------------
+template <typename T> struct cplx;
+template <> struct cplx<float> { using type = float2; };
+template <> struct cplx<double> { using type = double2; };
+template <typename T> using c_t = typename cplx<T>::type;
+
+template <typename T>
+__device__ __forceinline__ c_t<T> cmk(T re, T im) { c_t<T> r; r.x = re; r.y = im; return r; }
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// a * conj(b)
+template <typename C>
+__device__ __forceinline__ C cmulc(C a, C b) {
+    C r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.y * b.x - a.x * b.y;
+    return r;
+}
+
+// ----------------------------------------------------------------------------
+// Window polynomials: for stencil offset index r (0..2m-1) and cell fraction
+// f in [0,1), w_r(f) = sum_q coef[r*(deg+1)+q] y^q, y = 2f - 1.
+// ----------------------------------------------------------------------------
+constexpr int kMaxM = 16;
+constexpr int kMaxDeg = 24;
+
+// ----------------------------------------------------------------------------
+// Plan
+// ----------------------------------------------------------------------------
+struct FftAxisPlan {
+    int n = 0;                // transform length
+    int nrad = 0;             // number of radix stages
+    int radix[16] = {0};      // radices in application order
+    void *tw = nullptr;       // device twiddles exp(-2 pi i k/n), k = 0..n-1 (c_t<T>)
+};
+
+struct Bins {
+    int B[3] = {8, 8, 8};     // tile size in cells per axis
+    int nb[3] = {0, 0, 0};    // tiles per axis
+    int64_t nbins = 0;
+    int *counts = nullptr;    // per-bin point counts (device)
+    int *offsets = nullptr;   // exclusive scan of counts, nbins + 1 entries (device)
+};
+
+struct Subproblems {
+    int64_t count = 0;        // number of work items
+    int maxpts = 1024;        // points per item at most
+    int4 *items = nullptr;    // (bin, first sorted index, npts, 0) (device)
+    int64_t cap = 0;
+};
+
+struct nfft3_plan_impl {
+    int dtype = NFFT3_C128;
+    int m = 8;
+    double sigma = 2.0;
+    double b = 0.0;
+    int64_t N[3] = {0, 0, 0};
+    int64_t n[3] = {0, 0, 0};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t elt = 16;          // bytes per complex element
+
+    void *grid = nullptr;     // n0 n1 n2 complex
+    std::vector<void *> extra_grids;   // batched derivative fields
+    void *cdec[3] = {nullptr, nullptr, nullptr};   // deconvolution factors (real T)
+    FftAxisPlan fft[3];
+    void *wcoef = nullptr;    // window polynomial coefficients (real T), 2m*(deg+1)
+    int deg = 0;
+
+    // points
+    int64_t M = 0;
+    bool have_points = false;
+    int64_t cap_pts = 0;
+    double *xs = nullptr;     // sorted folded points, (M,3)
+    int *perm = nullptr;      // sorted position -> caller index
+    int *bin_of = nullptr;    // per caller index: bin id (scratch)
+    int *rank = nullptr;      // per caller index: rank inside bin (scratch)
+    int *flag = nullptr;      // device status word (non-finite points)
+    Bins bins;
+    Subproblems sub;
+    int64_t epoch = 0;        // bumps at every set_points
+};
+
+// Raise a kernel's dynamic-LDS limit above the 64 KiB default when needed.
+void allow_lds(const void *kernel, size_t bytes);
+
+// error helpers ---------------------------------------------------------------
+void set_hip_error(hipError_t e, const char *where);
+#define NFFT3_HIP_TRY(expr)                                              \
+    do {                                                                 \
+        hipError_t _e = (expr);                                          \
+        if (_e != hipSuccess) {                                          \
+            ::nfft3::set_hip_error(_e, #expr);                           \
+            return (_e == hipErrorOutOfMemory) ? NFFT3_ERR_OOM : NFFT3_ERR_HIP; \
+        }                                                                \
+    } while (0)
+#define NFFT3_LAUNCH_CHECK(where)                                        \
+    do {                                                                 \
+        hipError_t _e = hipGetLastError();                               \
+        if (_e != hipSuccess) {                                          \
+            ::nfft3::set_hip_error(_e, where);                           \
+            return NFFT3_ERR_HIP;                                        \
+        }                                                                \
+    } while (0)
+
+// host-side tables (api.hip) ---------------------------------------------------
+double bessel_i0(double x);
+void deconv_factors(int64_t Nd, int64_t nd, int m, double b, double *c);
+int window_poly(int m, double b, double tol, int cap_deg, std::vector<double> &coef);
+bool factor_radices(int n, std::vector<int> &rad);
+
+// stage launchers ---------------------------------------------------------------
+// FFT (fft.hip)
+int launch_grid_forward(nfft3_plan_impl *p, const void *fhat, void *grid, int deriv_axis);
+int launch_grid_adjoint(nfft3_plan_impl *p, void *grid, void *fhat);
+// points (points.hip)
+int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x);
+// window sums (interp.hip)
+int launch_interp(nfft3_plan_impl *p, const void *grid, void *f);
+int launch_spread(nfft3_plan_impl *p, const void *f, void *grid);
+int launch_grad(nfft3_plan_impl *p, const void *grid, const void *G, double *grad_x);
+int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);
+// batch (batch.hip)
+int launch_batch(int T, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out,
+                 int deriv_mask);
+
+}  // namespace nfft3
+
+struct nfft3_plan_s : nfft3::nfft3_plan_impl {};

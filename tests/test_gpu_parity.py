@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Stage tests compare one kernel stage with the numpy statement of the same
+windowed step (oracle.nfft_steps) to rounding; end-to-end tests compare with
+the direct-sum oracle (oracle.ndft_*) within the m/sigma/dtype tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import nfft_steps as ns
+import workloads
+from gpu_common import dot_tol, log, phi0, rand_coeffs, rand_points, rel, to_dev, tol, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["c128", "c64"]
+
+
+@pytest.fixture(scope="module")
+def nf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1605_01244_amd as mod
+    return mod
+
+
+def make_plan(nf, N, m, dtype, sigma=2.0):
+    return nf.Plan(N, sigma=sigma, m=m, dtype=torch_dtype(dtype), device="cuda:0")
+
+
+# ------------------------------------------------------------- stages ----
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N,sigma,m", [((8, 12, 16), 2.0, 3), ((32, 32, 32), 2.0, 6), ((16, 24, 20), 1.5, 4),
+                                       ((6, 10, 4), 2.0, 2)])
+def test_stage_grid_matches_fft_of_deconvolved(nf, N, sigma, m, dtype):
+    """Deconvolve + zero-pad + 3-D FFT equals numpy fftn of the textbook
+    deconvolved array (GPU window normalised: factor phi(0)^3)."""
+    log(f"stage_grid N={N} sigma={sigma} m={m} {dtype}")
+    fh = rand_coeffs(N, 1)
+    p = make_plan(nf, N, m, dtype, sigma)
+    for axis in (-1, 0, 2):
+        p.stage_grid(to_dev(fh, dtype), axis)
+        g = p.grid().cpu().numpy()
+        f2 = fh
+        if axis >= 0:
+            k = (np.arange(N[axis]) - N[axis] // 2).astype(float)
+            shape = [1, 1, 1]
+            shape[axis] = N[axis]
+            f2 = fh * (-2j * np.pi * k.reshape(shape))
+        ref = ns.oversampled_grid(f2, m, sigma) * phi0(m, sigma) ** 3
+        l2, li = rel(g, ref)
+        assert l2 < (1e-14 if dtype == "c128" else 2e-6), (axis, l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N,m,M", [((16, 16, 16), 4, 3000), ((8, 12, 10), 3, 777), ((32, 16, 8), 8, 1234)])
+def test_stage_interp_matches_window_sum(nf, N, m, M, dtype):
+    """Window sum of an arbitrary loaded grid vs the numpy window sum."""
+    log(f"stage_interp N={N} m={m} M={M} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    r = np.random.default_rng(5)
+    g = r.standard_normal(p.n) + 1j * r.standard_normal(p.n)
+    x = rand_points(M, 6)
+    p.set_points(to_dev(x))
+    p.load_grid(to_dev(g, dtype))
+    got = p.stage_interp().cpu().numpy()
+    ref = ns.interpolate(g, x, m, 2.0) / phi0(m, 2.0) ** 3
+    l2, li = rel(got, ref)
+    assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_stage_spread_matches_numpy(nf, dtype):
+    N, m, M = (12, 16, 8), 4, 900
+    log(f"stage_spread N={N} m={m} M={M} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    x = rand_points(M, 7)
+    r = np.random.default_rng(8)
+    f = r.standard_normal(M) + 1j * r.standard_normal(M)
+    p.set_points(to_dev(x))
+    p.stage_spread(to_dev(f, dtype))
+    got = p.grid().cpu().numpy()
+    ref = ns.spread(f, x, p.n, m, 2.0) / phi0(m, 2.0) ** 3
+    l2, li = rel(got, ref)
+    assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
+
+
+# ---------------------------------------------------------- end to end ----
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_smooth_uniform_case(nf, dtype):
+    """N = 32^3 smooth coefficients, 1e4 uniform points, sigma 2, m 6 (FP64)
+    and m 4 (FP32): every output against the direct sum."""
+    m = 6 if dtype == "c128" else 4
+    fh, x = workloads.smooth_uniform_case(32, 10_000)
+    log(f"smooth_uniform N=32 M=1e4 m={m} {dtype}")
+    p = make_plan(nf, fh.shape, m, dtype)
+    p.set_points(to_dev(x))
+    got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    ref = oracle.ndft_trafo(fh, x)
+    l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.3e} rel-linf {li:.3e} tol {tol(m, 2.0, dtype):.1e}")
+    assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 10])
+def test_error_vs_m(nf, m, dtype):
+    """Error against the direct sum stays under the estimate for every m."""
+    N = (16, 12, 20)
+    fh = rand_coeffs(N, 10 + m)
+    x = rand_points(700, 20 + m)
+    log(f"error_vs_m N={N} m={m} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    ref = oracle.ndft_trafo(fh, x)
+    err = np.max(np.abs(got - ref))
+    bound = ns.pst_error_bound(m, 2.0) * np.sum(np.abs(fh))
+    rounding = (1e-13 if dtype == "c128" else 3e-6) * np.sum(np.abs(fh))
+    assert err <= bound + rounding, (err, bound)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_single_mode_closed_form(nf, dtype):
+    """fhat = delta_{k*} gives exp(-2 pi i k*.x) at every corner of I_N."""
+    N = (16, 8, 12)
+    m = 8 if dtype == "c128" else 4
+    x = rand_points(500, 30)
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    corners = [(a, b, c) for a in (-8, 7) for b in (-4, 3) for c in (-6, 5)] + [(0, 0, 0), (3, -1, 2)]
+    for k in corners:
+        log(f"single_mode k={k} {dtype}")
+        fh = np.zeros(N, dtype=np.complex128)
+        fh[k[0] + 8, k[1] + 4, k[2] + 6] = 1.0
+        got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+        ref = np.exp(-2j * np.pi * (x @ np.asarray(k, float)))
+        assert np.max(np.abs(got - ref)) <= tol(m, 2.0, dtype), k
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_regular_grid_points(nf, dtype):
+    """Points on x_n = n/N - 1/2: the sum is fftn((-1)^{sum k} fhat) (Sec. 2.1)."""
+    N = (16, 16, 16)
+    m = 8 if dtype == "c128" else 4
+    fh = rand_coeffs(N, 31)
+    g = [np.arange(n) / n - 0.5 for n in N]
+    X = np.stack(np.meshgrid(*g, indexing="ij"), axis=-1).reshape(-1, 3)
+    k0, k1, k2 = np.meshgrid(*[np.arange(n) - n // 2 for n in N], indexing="ij")
+    s = 1 - 2 * ((k0 + k1 + k2) & 1)
+    ref = np.fft.fftn(np.fft.ifftshift(fh * s)).reshape(-1)
+    log(f"regular_grid {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(X))
+    got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    l2, li = rel(got, ref)
+    assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_folding_and_edges(nf, dtype):
+    """Points at -1/2, just below +1/2, exactly +1/2 (= -1/2) and shifted by
+    integers evaluate as their folded copies."""
+    N = (8, 8, 8)
+    m = 6 if dtype == "c128" else 4
+    fh = rand_coeffs(N, 32)
+    base = np.array([[-0.5, -0.5, -0.5], [0.5 - 1e-16, 0.25, -0.125], [0.0, 0.0, 0.0],
+                     [0.3, -0.49999999, 0.4999999999]])
+    shifted = base + np.array([[3.0, -7.0, 1.0], [-2.0, 0.0, 5.0], [1.0, 1.0, -1.0], [0.0, 2.0, -4.0]])
+    halfplus = np.array([[0.5, 0.5, 0.5]])
+    x = np.concatenate([base, shifted, halfplus])
+    log(f"folding {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    ref = oracle.ndft_trafo(fh, x)
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= tol(m, 2.0, dtype)
+    assert np.max(np.abs(got[:4] - got[4:8])) <= 10 * tol(m, 2.0, dtype) * np.max(np.abs(ref))
+    assert abs(got[8] - got[0]) <= 10 * tol(m, 2.0, dtype) * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N,sigma", [((2, 2, 2), 2.0), ((4, 6, 2), 2.0), ((12, 8, 20), 1.5), ((10, 10, 10), 2.0),
+                                     ((64, 4, 8), 2.0)])
+def test_shapes_and_sigma(nf, N, sigma, dtype):
+    """Small, non-cubic, radix-3/5 and sigma = 1.5 grids."""
+    m = min(4, min(int(sigma * n) for n in N) // 2)
+    fh = rand_coeffs(N, 33)
+    x = rand_points(333, 34)
+    log(f"shapes N={N} sigma={sigma} m={m} {dtype}")
+    p = make_plan(nf, N, m, dtype, sigma)
+    p.set_points(to_dev(x))
+    got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    ref = oracle.ndft_trafo(fh, x)
+    err = np.max(np.abs(got - ref))
+    bound = ns.pst_error_bound(m, sigma) * np.sum(np.abs(fh))
+    assert err <= bound + (1e-13 if dtype == "c128" else 3e-6) * np.sum(np.abs(fh)), (err, bound)
+
+
+def test_empty_points_and_errors(nf):
+    import torch
+    N = (8, 8, 8)
+    p = make_plan(nf, N, 4, "c128")
+    fh = to_dev(rand_coeffs(N, 35), "c128")
+    log("errors: no points")
+    with pytest.raises(nf.NFFT3Error) as e:
+        p.trafo(fh, out=torch.empty(0, dtype=torch.complex128, device="cuda:0"))
+    assert e.value.code == -4
+    p.set_points(torch.zeros((0, 3), dtype=torch.float64, device="cuda:0"))
+    out = p.trafo(fh)
+    assert out.numel() == 0
+    adj = p.adjoint(torch.zeros(0, dtype=torch.complex128, device="cuda:0"))
+    assert torch.count_nonzero(adj).item() == 0
+    log("errors: non-finite")
+    bad = torch.tensor([[0.1, float("nan"), 0.2], [0.0, 0.0, 0.0]], dtype=torch.float64, device="cuda:0")
+    with pytest.raises(nf.NFFT3Error) as e:
+        p.set_points(bad)
+    assert e.value.code == -5
+    with pytest.raises(nf.NFFT3Error) as e:
+        p.trafo(fh, out=torch.empty(0, dtype=torch.complex128, device="cuda:0"))
+    assert e.value.code == -4
+    bad = torch.tensor([[0.1, float("inf"), 0.2]], dtype=torch.float64, device="cuda:0")
+    with pytest.raises(nf.NFFT3Error):
+        p.set_points(bad)
+
+
+# ------------------------------------------------------------- adjoint ----
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_adjoint_dot_product_and_direct_sum(nf, dtype):
+    N = (16, 12, 20)
+    m = 8 if dtype == "c128" else 4
+    fh = rand_coeffs(N, 40)
+    x = rand_points(2000, 41)
+    r = np.random.default_rng(42)
+    y = r.standard_normal(2000) + 1j * r.standard_normal(2000)
+    log(f"adjoint N={N} m={m} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    Af = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    Ahy = p.adjoint(to_dev(y, dtype)).cpu().numpy()
+    lhs = np.vdot(y, Af)
+    rhs = np.vdot(Ahy, fh)
+    assert abs(lhs - rhs) / abs(lhs) < dot_tol(dtype)
+    ref = oracle.ndft_adjoint(y, x, N)
+    l2, li = rel(Ahy, ref)
+    assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (l2, li)
+
+
+# ---------------------------------------------------------------- grad ----
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_grad_points_vs_direct_derivative(nf, dtype):
+    N = (16, 16, 12)
+    m = 8 if dtype == "c128" else 4
+    fh = rand_coeffs(N, 50)
+    x = rand_points(1500, 51)
+    r = np.random.default_rng(52)
+    G = r.standard_normal(1500) + 1j * r.standard_normal(1500)
+    log(f"grad N={N} m={m} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    got = p.grad_points(to_dev(fh, dtype), to_dev(G, dtype)).cpu().numpy()
+    D = oracle.ndft_grad(fh, x)
+    ref = (np.conj(G)[:, None] * D).real
+    l2, li = rel(got, ref)
+    gate = 10 * tol(m, 2.0, dtype)
+    assert l2 <= gate and li <= gate, (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_derivative_fields(nf, dtype):
+    """trafo_fields: the field and the three fields of -2 pi i k_d fhat."""
+    N = (12, 16, 8)
+    m = 8 if dtype == "c128" else 4
+    fh = rand_coeffs(N, 60)
+    x = rand_points(800, 61)
+    log(f"fields N={N} m={m} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    out = p.trafo_fields(to_dev(fh, dtype), 7).cpu().numpy()
+    ref0 = oracle.ndft_trafo(fh, x)
+    D = oracle.ndft_grad(fh, x)
+    for i, ref in enumerate([ref0, D[:, 0], D[:, 1], D[:, 2]]):
+        l2, li = rel(out[i], ref)
+        assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (i, l2, li)
+    out5 = p.trafo_fields(to_dev(fh, dtype), 5).cpu().numpy()
+    assert out5.shape[0] == 3
+    assert np.allclose(out5[1], out[1]) and np.allclose(out5[2], out[3])
