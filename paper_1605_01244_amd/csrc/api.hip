@@ -166,6 +166,9 @@ static void free_plan(nfft3_plan_impl *p) {
     hipFree(p->flag);
     hipFree(p->bins.counts);
     hipFree(p->bins.offsets);
+    hipFree(p->bins.scratch);
+    hipFree(p->bins.tile_items);
+    hipFree(p->bins.tile_item_off);
     hipFree(p->sub.items);
 }
 
@@ -247,19 +250,22 @@ static int build_plan(nfft3_plan_impl *p) {
     p->deg = deg;
     int rc = f64 ? upload_real<double>(coef, &p->wcoef) : upload_real<float>(coef, &p->wcoef);
     if (rc) return rc;
-    // bins: tiles of 8 cells (more for very large grids)
-    int64_t nb = 1;
-    for (int d = 0; d < 3; ++d) {
-        int B = 8;
-        while (p->n[d] / B > 64) B *= 2;
-        if (B > p->n[d]) B = (int)p->n[d];
-        p->bins.B[d] = B;
-        p->bins.nb[d] = (int)((p->n[d] + B - 1) / B);
-        nb *= p->bins.nb[d];
-    }
+    // point tiles: the largest power of two <= 32 whose plane (tile + stencil
+    // halo) fits the window-sum kernels' staging (kMaxPlane elements)
+    int T = 32;
+    while (T > 1 && (T + 2 * p->m - 1) * (T + 2 * p->m - 1) > kMaxPlane) T /= 2;
+    p->bins.By = (int)std::min<int64_t>(T, p->n[1]);
+    p->bins.Bx = (int)std::min<int64_t>(T, p->n[2]);
+    p->bins.nty = (int)((p->n[1] + p->bins.By - 1) / p->bins.By);
+    p->bins.ntx = (int)((p->n[2] + p->bins.Bx - 1) / p->bins.Bx);
+    const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
+    const int64_t nb = ntiles * p->n[0];
     p->bins.nbins = nb;
     NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nb));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nb + 1)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nb / 1024 + 2)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * ntiles));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (ntiles + 1)));
     return NFFT3_OK;
 }
 

@@ -60,18 +60,27 @@ struct FftAxisPlan {
     void *tw = nullptr;       // device twiddles exp(-2 pi i k/n), k = 0..n-1 (c_t<T>)
 };
 
+// Points are sorted by (tile, z-cell); a tile is By x Bx cells of the (y, x)
+// plane.  Work items for the window-sum kernels are at most kItemPts points of
+// one tile column spanning at most kItemZ z-cells.
+constexpr int kItemPts = 256;
+constexpr int kItemZ = 64;
+constexpr int kMaxPlane = 12 * kItemPts;   // staged plane elements per workgroup
+
 struct Bins {
-    int B[3] = {8, 8, 8};     // tile size in cells per axis
-    int nb[3] = {0, 0, 0};    // tiles per axis
-    int64_t nbins = 0;
+    int By = 32, Bx = 32;     // tile size in cells (y, x)
+    int nty = 0, ntx = 0;     // tiles per axis
+    int64_t nbins = 0;        // nty * ntx * n0
     int *counts = nullptr;    // per-bin point counts (device)
     int *offsets = nullptr;   // exclusive scan of counts, nbins + 1 entries (device)
+    int *scratch = nullptr;   // block sums of the scans
+    int *tile_items = nullptr;      // items per tile (device)
+    int *tile_item_off = nullptr;   // exclusive scan, ntiles + 1 entries (device)
 };
 
 struct Subproblems {
     int64_t count = 0;        // number of work items
-    int maxpts = 1024;        // points per item at most
-    int4 *items = nullptr;    // (bin, first sorted index, npts, 0) (device)
+    int4 *items = nullptr;    // (tile, first sorted index, end sorted index, 0) (device)
     int64_t cap = 0;
 };
 

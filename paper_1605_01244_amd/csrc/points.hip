@@ -1,16 +1,19 @@
 // Point preprocessing (the precomputation step of the windowed method):
 // fold every point into [-1/2, 1/2) with the Euclidean remainder of
 // Sec. 2.2.1, locate its grid cell u_d = floor(n_d x_d) in FP64, and sort the
-// points by grid tile with a counting sort (histogram -> exclusive scan ->
-// scatter).  The sorted copy keeps the folded FP64 coordinates and the
-// permutation back to the caller's order, so a workgroup of the window-sum
-// kernels touches one compact region of the grid.
+// points with a counting sort (histogram -> exclusive scan -> scatter) by the
+// key (tile, z-cell), where a tile is a By x Bx block of cells in the (y, x)
+// plane and z (axis 0) varies fastest.  Each tile column is then cut into
+// work items of at most kItemPts points spanning at most kItemZ z-cells; a
+// workgroup of the window-sum kernels takes one item and streams the z-planes
+// of its tile (plus the stencil halo) through LDS.
 #include "internal.h"
 
 namespace nfft3 {
 
 constexpr int kPtThreads = 256;
-constexpr int kScanThreads = 1024;
+constexpr int kScanBlock = 1024;     // elements per block of the scan
+constexpr int kScanThreads = 256;
 
 __device__ __forceinline__ double fold_unit(double v) {
     double r = v - rint(v);          // exact; in [-1/2, 1/2]
@@ -20,8 +23,8 @@ __device__ __forceinline__ double fold_unit(double v) {
 struct BinGeom {
     double n0, n1, n2;
     int in0, in1, in2;
-    int B0, B1, B2;
-    int nb0, nb1, nb2;
+    int By, Bx;
+    int nty, ntx;
 };
 
 __device__ __forceinline__ int cell_of(double r, double nd, int ind) {
@@ -34,7 +37,7 @@ __device__ __forceinline__ int bin_of_point(const double *xp, const BinGeom &g) 
     const int c0 = cell_of(fold_unit(xp[0]), g.n0, g.in0);
     const int c1 = cell_of(fold_unit(xp[1]), g.n1, g.in1);
     const int c2 = cell_of(fold_unit(xp[2]), g.n2, g.in2);
-    return ((c0 / g.B0) * g.nb1 + c1 / g.B1) * g.nb2 + c2 / g.B2;
+    return ((c1 / g.By) * g.ntx + c2 / g.Bx) * g.in0 + c0;
 }
 
 __global__ void fill_int_kernel(int *p, int64_t count, int v) {
@@ -58,29 +61,76 @@ bin_count_kernel(const double *__restrict__ x, int64_t M, BinGeom g, int *__rest
     rank[j] = atomicAdd(&counts[b], 1);
 }
 
-// Exclusive scan of nb counts by one workgroup (nb is at most a few 1e5).
-__global__ void __launch_bounds__(kScanThreads)
-scan_kernel(const int *__restrict__ counts, int *__restrict__ offsets, int64_t nb) {
-    __shared__ int part[kScanThreads];
+// ---- exclusive scan: block-local scans, a scan of block sums, then add ------
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total) {
     const int tid = threadIdx.x;
-    const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
-    const int64_t lo = min<int64_t>(nb, tid * per), hi = min<int64_t>(nb, lo + per);
-    int s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += counts[i];
-    part[tid] = s;
+    sh[tid] = v;
     __syncthreads();
     for (int off = 1; off < kScanThreads; off <<= 1) {
-        int v = tid >= off ? part[tid - off] : 0;
+        int t = tid >= off ? sh[tid - off] : 0;
         __syncthreads();
-        part[tid] += v;
+        sh[tid] += t;
         __syncthreads();
     }
-    int run = part[tid] - s;   // exclusive prefix of this chunk
-    for (int64_t i = lo; i < hi; ++i) {
-        offsets[i] = run;
-        run += counts[i];
+    total = sh[kScanThreads - 1];
+    int ex = sh[tid] - v;
+    __syncthreads();
+    return ex;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+scan_blocks_kernel(const int *__restrict__ in, int *__restrict__ out, int *__restrict__ block_sums, int64_t n) {
+    __shared__ int sh[kScanThreads];
+    constexpr int per = kScanBlock / kScanThreads;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * per;
+    int v[per];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0;
+        s += v[i];
     }
-    if (tid == kScanThreads - 1) offsets[nb] = part[tid];
+    int total;
+    int run = block_exclusive_scan(s, sh, total);
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single workgroup: exclusive scan of nb block sums in place; writes the total
+__global__ void __launch_bounds__(kScanThreads)
+scan_sums_kernel(int *__restrict__ sums, int64_t nb, int *__restrict__ total_out) {
+    __shared__ int sh[kScanThreads];
+    int carry = 0;
+    for (int64_t start = 0; start < nb; start += kScanThreads) {
+        const int64_t i = start + threadIdx.x;
+        int v = i < nb ? sums[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, sh, total);
+        if (i < nb) sums[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void add_block_offsets_kernel(int *__restrict__ out, const int *__restrict__ sums, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += sums[i / kScanBlock];
+}
+
+// exclusive scan of n ints (in -> out), out[n] = total; sums needs ceil(n/1024) ints
+static int exclusive_scan(hipStream_t s, const int *in, int *out, int *sums, int64_t n) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, sums, n);
+    NFFT3_LAUNCH_CHECK("scan_blocks_kernel");
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, sums, nb, out + n);
+    NFFT3_LAUNCH_CHECK("scan_sums_kernel");
+    hipLaunchKernelGGL(add_block_offsets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, sums, n);
+    NFFT3_LAUNCH_CHECK("add_block_offsets_kernel");
+    return NFFT3_OK;
 }
 
 __global__ void __launch_bounds__(kPtThreads)
@@ -97,31 +147,96 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
     perm[pos] = (int)j;
 }
 
+// ---- work items: walk each tile column's z-cells (one thread per tile) ------
+// A new item starts when adding the next cell would exceed kItemPts points or
+// the item would span more than kItemZ z-cells; a cell holding more than
+// kItemPts points becomes ceil(count/kItemPts) items of its own.  WRITE=false
+// counts the items of each tile, WRITE=true emits (tile, p_lo, p_hi, 0).
+template <bool WRITE>
+__global__ void __launch_bounds__(256)
+items_kernel(const int *__restrict__ counts, const int *__restrict__ offsets, int ntiles, int n0,
+             int *__restrict__ item_count, const int *__restrict__ item_offset, int4 *__restrict__ items) {
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    const int *cnt = counts + (int64_t)tile * n0;
+    const int *off = offsets + (int64_t)tile * n0;
+    int k = 0;
+    int64_t w = WRITE ? item_offset[tile] : 0;
+    int cur = 0, z_start = 0, p_start = 0;
+    for (int z = 0; z < n0; ++z) {
+        const int c = cnt[z];
+        if (c == 0) continue;
+        if (cur > 0 && (cur + c > kItemPts || z - z_start >= kItemZ)) {
+            if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
+            ++k;
+            cur = 0;
+        }
+        if (c > kItemPts) {   // a dense cell on its own
+            for (int s = 0; s < c; s += kItemPts) {
+                if (WRITE) items[w + k] = make_int4(tile, off[z] + s, off[z] + min(c, s + kItemPts), 0);
+                ++k;
+            }
+            continue;
+        }
+        if (cur == 0) { z_start = z; p_start = off[z]; }
+        cur += c;
+    }
+    if (cur > 0) {
+        if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
+        ++k;
+    }
+    if (!WRITE) item_count[tile] = k;
+}
+
 int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     BinGeom g;
     g.n0 = (double)p->n[0]; g.n1 = (double)p->n[1]; g.n2 = (double)p->n[2];
     g.in0 = (int)p->n[0]; g.in1 = (int)p->n[1]; g.in2 = (int)p->n[2];
-    g.B0 = p->bins.B[0]; g.B1 = p->bins.B[1]; g.B2 = p->bins.B[2];
-    g.nb0 = p->bins.nb[0]; g.nb1 = p->bins.nb[1]; g.nb2 = p->bins.nb[2];
+    g.By = p->bins.By; g.Bx = p->bins.Bx;
+    g.nty = p->bins.nty; g.ntx = p->bins.ntx;
     const int64_t nb = p->bins.nbins;
-    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, p->stream,
-                       p->bins.counts, nb, 0);
+    const int ntiles = p->bins.nty * p->bins.ntx;
+    hipStream_t s = p->stream;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, p->bins.counts, nb, 0);
     NFFT3_LAUNCH_CHECK("fill_int_kernel");
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, p->stream, p->flag, (int64_t)16, 0);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, s, p->flag, (int64_t)16, 0);
     NFFT3_LAUNCH_CHECK("fill_int_kernel");
     const unsigned blocks = (unsigned)((M + kPtThreads - 1) / kPtThreads);
     if (M > 0) {
-        hipLaunchKernelGGL(bin_count_kernel, dim3(blocks), dim3(kPtThreads), 0, p->stream, x, M, g,
-                           p->bins.counts, p->bin_of, p->rank, p->flag);
+        hipLaunchKernelGGL(bin_count_kernel, dim3(blocks), dim3(kPtThreads), 0, s, x, M, g, p->bins.counts,
+                           p->bin_of, p->rank, p->flag);
         NFFT3_LAUNCH_CHECK("bin_count_kernel");
     }
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, p->stream, p->bins.counts,
-                       p->bins.offsets, nb);
-    NFFT3_LAUNCH_CHECK("scan_kernel");
+    int rc = exclusive_scan(s, p->bins.counts, p->bins.offsets, p->bins.scratch, nb);
+    if (rc) return rc;
     if (M > 0) {
-        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kPtThreads), 0, p->stream, x, M,
-                           p->bins.offsets, p->bin_of, p->rank, p->xs, p->perm);
+        hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kPtThreads), 0, s, x, M, p->bins.offsets,
+                           p->bin_of, p->rank, p->xs, p->perm);
         NFFT3_LAUNCH_CHECK("scatter_kernel");
+    }
+    // work items
+    const unsigned tb = (unsigned)((ntiles + 255) / 256);
+    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(256), 0, s, p->bins.counts, p->bins.offsets, ntiles,
+                       g.in0, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr);
+    NFFT3_LAUNCH_CHECK("items_kernel");
+    rc = exclusive_scan(s, p->bins.tile_items, p->bins.tile_item_off, p->bins.scratch, ntiles);
+    if (rc) return rc;
+    // the item count is needed on the host to size the item list and the launches
+    int nitems = 0;
+    NFFT3_HIP_TRY(hipMemcpyAsync(&nitems, p->bins.tile_item_off + ntiles, sizeof(int), hipMemcpyDeviceToHost, s));
+    NFFT3_HIP_TRY(hipStreamSynchronize(s));
+    if (nitems > p->sub.cap) {
+        hipFree(p->sub.items);
+        p->sub.items = nullptr;
+        p->sub.cap = 0;
+        NFFT3_HIP_TRY(hipMalloc(&p->sub.items, sizeof(int4) * (size_t)std::max(nitems, 1)));
+        p->sub.cap = nitems;
+    }
+    p->sub.count = nitems;
+    if (nitems > 0) {
+        hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(256), 0, s, p->bins.counts, p->bins.offsets, ntiles,
+                           g.in0, (int *)nullptr, (const int *)p->bins.tile_item_off, p->sub.items);
+        NFFT3_LAUNCH_CHECK("items_kernel");
     }
     return NFFT3_OK;
 }
