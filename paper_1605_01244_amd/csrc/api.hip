@@ -258,6 +258,9 @@ static int build_plan(nfft3_plan_impl *p) {
     p->bins.Bx = (int)std::min<int64_t>(T, p->n[2]);
     p->bins.nty = (int)((p->n[1] + p->bins.By - 1) / p->bins.By);
     p->bins.ntx = (int)((p->n[2] + p->bins.Bx - 1) / p->bins.Bx);
+    // points per thread of the interpolation kernel (registers hold the y/x
+    // weights of every point a thread owns)
+    p->sub.maxpts = kItemPts * (f64 ? 2 : 1);
     const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
     const int64_t nb = ntiles * p->n[0];
     p->bins.nbins = nb;

@@ -18,7 +18,6 @@
 
 namespace nfft3 {
 
-constexpr int kFftThreads = 256;
 constexpr int kMaxStages = 16;
 
 struct RadixList {
@@ -114,82 +113,122 @@ __device__ __forceinline__ void dft_small(c_t<T> *v) {
     else dft8<T, FWD>(v);
 }
 
-// ------------------------------------------------------ Stockham stage ----
-// One radix-R stage over `nlines` lines of length n held in LDS (line stride
-// ls).  Butterfly j of a line reads x[j + r n/R], twiddles by
-// W^{r (j mod Ns) n/(Ns R)}, W = exp(-+2 pi i/n), and writes the R results to
-// (j/Ns) Ns R + (j mod Ns) + r Ns.  All reads complete (barrier) before any
-// write, so a single buffer suffices.
-template <typename T, int R, int VMAX, bool FWD>
-__device__ __forceinline__ void stockham_stage(c_t<T> *buf, int ls, int nlines, int n, int Ns,
-                                               const c_t<T> *__restrict__ tw, int tid) {
+// ------------------------------------------------------ Stockham engine ----
+// Radix-R stage over `nlines` lines of length n: butterfly j of a line reads
+// x[j + r n/R], twiddles by W^{r (j mod Ns) n/(Ns R)} (W = exp(-+2 pi i/n)) and
+// writes its R results to (j/Ns) Ns R + (j mod Ns) + r Ns.  The first stage
+// reads its inputs through `ld` straight from global memory (zero-padding is
+// never loaded), the last stage writes through `st` straight to global memory
+// (for the last stage Ns = n/R, so the outputs land at j + r n/R); only the
+// stages in between go through LDS, in place: every read of a stage completes
+// (barrier) before any of its writes.
+//
+// Butterfly -> (line, j) mapping: LINE_FAST puts consecutive lanes on
+// consecutive lines (strided-axis tiles: lines are adjacent columns in memory,
+// so a wave's loads are contiguous); otherwise consecutive lanes take
+// consecutive j of one line (contiguous rows).
+template <bool LINE_FAST>
+__device__ __forceinline__ void bt_map(int bt, int nlines, int nbl, int &line, int &j) {
+    if (LINE_FAST) { j = bt / nlines; line = bt - j * nlines; }
+    else { line = bt / nbl; j = bt - line * nbl; }
+}
+
+template <typename T, int R, int VMAX, int NT, bool FWD, bool LINE_FAST, bool FIRST, bool LAST, class LD, class ST>
+__device__ __forceinline__ void fft_stage(c_t<T> *buf, int ls, int nlines, int n, int Ns,
+                                          const c_t<T> *__restrict__ tw, LD &ld, ST &st) {
     constexpr int BMAX = VMAX / R;
+    const int tid = threadIdx.x;
     const int nbl = n / R;
     const int NB = nlines * nbl;
     c_t<T> v[BMAX][R];
 #pragma unroll
     for (int i = 0; i < BMAX; ++i) {
-        const int bt = tid + i * kFftThreads;
+        const int bt = tid + i * NT;
         if (bt < NB) {
-            const int line = bt / nbl, j = bt - line * nbl;
-            const c_t<T> *src = buf + line * ls;
+            int line, j;
+            bt_map<LINE_FAST>(bt, nlines, nbl, line, j);
+            if (FIRST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = src[j + r * nbl];
+                for (int r = 0; r < R; ++r) v[i][r] = ld(line, j + r * nbl);
+            } else {
+                const c_t<T> *src = buf + line * ls;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = src[j + r * nbl];
+            }
         }
     }
-    __syncthreads();
+    if (!FIRST && !LAST) __syncthreads();
     const int step = n / (Ns * R);
 #pragma unroll
     for (int i = 0; i < BMAX; ++i) {
-        const int bt = tid + i * kFftThreads;
+        const int bt = tid + i * NT;
         if (bt < NB) {
-            const int line = bt / nbl, j = bt - line * nbl;
+            int line, j;
+            bt_map<LINE_FAST>(bt, nlines, nbl, line, j);
             const int k = j % Ns;
-            if (Ns > 1) {
+            if (!FIRST && Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    c_t<T> w = tw[r * k * step];
+                    const c_t<T> w = tw[r * k * step];
                     v[i][r] = FWD ? cmul(v[i][r], w) : cmulc(v[i][r], w);
                 }
             }
             dft_small<T, R, FWD>(v[i]);
-            c_t<T> *dst = buf + line * ls;
-            const int base = (j / Ns) * Ns * R + k;
+            if (LAST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[i][r];
+                for (int r = 0; r < R; ++r) st(line, j + r * nbl, v[i][r]);
+            } else {
+                c_t<T> *dst = buf + line * ls;
+                const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[i][r];
+            }
         }
     }
-    __syncthreads();
+    if (!LAST) __syncthreads();
 }
 
-template <typename T, int VMAX, bool FWD>
-__device__ __forceinline__ void stockham_lines(c_t<T> *buf, int ls, int nlines, int n, const RadixList &rl,
-                                               const c_t<T> *__restrict__ tw, int tid) {
-    int Ns = 1;
-    for (int s = 0; s < rl.nrad; ++s) {
-        const int R = rl.r[s];
-        switch (R) {
-            case 8: stockham_stage<T, 8, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
-            case 4: stockham_stage<T, 4, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
-            case 2: stockham_stage<T, 2, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
-            case 3: stockham_stage<T, 3, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
-            default: stockham_stage<T, 5, VMAX, FWD>(buf, ls, nlines, n, Ns, tw, tid); break;
-        }
-        Ns *= R;
+template <typename T, int VMAX, int NT, bool FWD, bool LINE_FAST, bool FIRST, bool LAST, class LD, class ST>
+__device__ __forceinline__ void fft_stage_r(int R, c_t<T> *buf, int ls, int nlines, int n, int Ns,
+                                            const c_t<T> *__restrict__ tw, LD &ld, ST &st) {
+    switch (R) {
+        case 8: fft_stage<T, 8, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
+        case 4: fft_stage<T, 4, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
+        case 2: fft_stage<T, 2, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
+        case 3: fft_stage<T, 3, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
+        default: fft_stage<T, 5, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
     }
 }
 
-__device__ __forceinline__ int wrap_pos(int i, int L, int n) {
-    int p = i - L / 2;
-    return p < 0 ? p + n : p;
+template <typename T, int VMAX, int NT, bool FWD, bool LINE_FAST, class LD, class ST>
+__device__ __forceinline__ void fft_lines(c_t<T> *buf, int ls, int nlines, int n, const RadixList &rl,
+                                          const c_t<T> *__restrict__ tw, LD &ld, ST &st) {
+    if (rl.nrad == 1) {
+        fft_stage_r<T, VMAX, NT, FWD, LINE_FAST, true, true>(rl.r[0], buf, ls, nlines, n, 1, tw, ld, st);
+        return;
+    }
+    int Ns = rl.r[0];
+    fft_stage_r<T, VMAX, NT, FWD, LINE_FAST, true, false>(rl.r[0], buf, ls, nlines, n, 1, tw, ld, st);
+    for (int s = 1; s + 1 < rl.nrad; ++s) {
+        fft_stage_r<T, VMAX, NT, FWD, LINE_FAST, false, false>(rl.r[s], buf, ls, nlines, n, Ns, tw, ld, st);
+        Ns *= rl.r[s];
+    }
+    fft_stage_r<T, VMAX, NT, FWD, LINE_FAST, false, true>(rl.r[rl.nrad - 1], buf, ls, nlines, n, Ns, tw, ld, st);
+}
+
+// FFT position -> compact index of a pruned line of L entries (frequency
+// k = pos or pos - n; kept when -L/2 <= k < L/2), or -1.
+__device__ __forceinline__ int compact_of(int pos, int L, int n) {
+    const int k = pos < n / 2 ? pos : pos - n;
+    return (k >= -L / 2 && k < L / 2) ? k + L / 2 : -1;
 }
 
 // -------------------------------------------------------- row passes ----
-// MODE 0 (forward, first pass): rows (i0,i1) of fhat, deconvolved by
-//   c0[i0] c1[i1] c2[i2] (times -2 pi i k_d for a derivative field), placed at
-//   wrap_pos(i2) and transformed; all n outputs stored to grid rows (i0,i1).
-// MODE 1 (adjoint, last pass): grid rows (i0,i1), transformed with + sign;
-//   the N2 outputs at wrap_pos(o) times c0 c1 c2 stored to fhat.
+// MODE 0 (forward, first pass): rows (i0,i1) of fhat deconvolved by
+//   c0[i0] c1[i1] c2[i2] (times -2 pi i k_d for a derivative field) at FFT
+//   position of i2; all n outputs stored to grid rows (i0,i1).
+// MODE 1 (adjoint, last pass): grid rows (i0,i1) transformed with + sign; the
+//   N2 kept outputs times c0 c1 c2 stored to fhat.
 struct RowArgs {
     const void *in;
     void *out;
@@ -202,69 +241,67 @@ struct RowArgs {
     RadixList rl;
 };
 
+constexpr int kRowThreads = 256;
+
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kFftThreads) fft_rows_kernel(RowArgs a) {
+__global__ void __launch_bounds__(kRowThreads) fft_rows_kernel(RowArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c_t<T> *buf = reinterpret_cast<c_t<T> *>(smem_raw);
-    const int tid = threadIdx.x;
     const int n = a.n;
-    const int ls = n;
     const int64_t nrows = (int64_t)a.N0 * a.N1;
     const int64_t row0 = (int64_t)blockIdx.x * a.lpw;
     const int nl = (int)min<int64_t>(a.lpw, nrows - row0);
     const T *c0 = (const T *)a.c0, *c1 = (const T *)a.c1, *c2 = (const T *)a.c2;
     const T twopi = (T)6.283185307179586476925286766559;
+    const int N0 = a.N0, N1 = a.N1, N2 = a.N2, deriv = a.deriv;
+    const int64_t s0 = a.grid_s0, s1 = a.grid_s1;
 
+    // rows handled here are (i0, i1) = divmod(row0 + line, N1); 32-bit index math
+    const int rbase = (int)row0;
     if (MODE == 0) {
         const c_t<T> *fhat = (const c_t<T> *)a.in;
-        // zero the padded positions, then place the N2 deconvolved inputs
-        for (int idx = tid; idx < nl * n; idx += kFftThreads) buf[idx] = cmk<T>(0, 0);
-        __syncthreads();
-        for (int idx = tid; idx < nl * a.N2; idx += kFftThreads) {
-            const int l = idx / a.N2, i2 = idx - l * a.N2;
-            const int64_t row = row0 + l;
-            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
-            c_t<T> v = fhat[row * a.N2 + i2];
-            T s = c0[i0] * c1[i1] * c2[i2];
+        c_t<T> *grid = (c_t<T> *)a.out;
+        auto ld = [&](int line, int pos) -> c_t<T> {
+            const int i2 = compact_of(pos, N2, n);
+            if (i2 < 0) return cmk<T>(0, 0);
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            c_t<T> v = fhat[(int64_t)row * N2 + i2];
+            const T s = c0[i0] * c1[i1] * c2[i2];
             v.x *= s;
             v.y *= s;
-            if (a.deriv >= 0) {   // times -2 pi i k_d
-                const int kd = a.deriv == 0 ? i0 - a.N0 / 2 : a.deriv == 1 ? i1 - a.N1 / 2 : i2 - a.N2 / 2;
+            if (deriv >= 0) {   // times -2 pi i k_d
+                const int kd = deriv == 0 ? i0 - N0 / 2 : deriv == 1 ? i1 - N1 / 2 : i2 - N2 / 2;
                 const T f = twopi * (T)kd;
                 v = cmk<T>(f * v.y, -f * v.x);
             }
-            buf[l * ls + wrap_pos(i2, a.N2, n)] = v;
-        }
-        __syncthreads();
-        stockham_lines<T, 16, true>(buf, ls, nl, n, a.rl, (const c_t<T> *)a.tw, tid);
-        c_t<T> *grid = (c_t<T> *)a.out;
-        for (int idx = tid; idx < nl * n; idx += kFftThreads) {
-            const int l = idx / n, x = idx - l * n;
-            const int64_t row = row0 + l;
-            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
-            grid[i0 * a.grid_s0 + i1 * a.grid_s1 + x] = buf[l * ls + x];
-        }
+            return v;
+        };
+        auto st = [&](int line, int pos, c_t<T> v) {
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            grid[i0 * s0 + i1 * s1 + pos] = v;
+        };
+        fft_lines<T, 16, kRowThreads, true, false>(buf, n, nl, n, a.rl, (const c_t<T> *)a.tw, ld, st);
     } else {
         const c_t<T> *grid = (const c_t<T> *)a.in;
-        for (int idx = tid; idx < nl * n; idx += kFftThreads) {
-            const int l = idx / n, x = idx - l * n;
-            const int64_t row = row0 + l;
-            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
-            buf[l * ls + x] = grid[i0 * a.grid_s0 + i1 * a.grid_s1 + x];
-        }
-        __syncthreads();
-        stockham_lines<T, 16, false>(buf, ls, nl, n, a.rl, (const c_t<T> *)a.tw, tid);
         c_t<T> *fhat = (c_t<T> *)a.out;
-        for (int idx = tid; idx < nl * a.N2; idx += kFftThreads) {
-            const int l = idx / a.N2, o = idx - l * a.N2;
-            const int64_t row = row0 + l;
-            const int i0 = (int)(row / a.N1), i1 = (int)(row - (int64_t)i0 * a.N1);
-            c_t<T> v = buf[l * ls + wrap_pos(o, a.N2, n)];
-            T s = c0[i0] * c1[i1] * c2[o];
+        auto ld = [&](int line, int pos) -> c_t<T> {
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            return grid[i0 * s0 + i1 * s1 + pos];
+        };
+        auto st = [&](int line, int pos, c_t<T> v) {
+            const int o = compact_of(pos, N2, n);
+            if (o < 0) return;
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            const T s = c0[i0] * c1[i1] * c2[o];
             v.x *= s;
             v.y *= s;
-            fhat[row * a.N2 + o] = v;
-        }
+            fhat[(int64_t)row * N2 + o] = v;
+        };
+        fft_lines<T, 16, kRowThreads, false, false>(buf, n, nl, n, a.rl, (const c_t<T> *)a.tw, ld, st);
     }
 }
 
@@ -272,8 +309,8 @@ __global__ void __launch_bounds__(kFftThreads) fft_rows_kernel(RowArgs a) {
 // In-place transform along a strided axis of tiles of C adjacent columns.
 // Column c of tile (outer, x0) has element i at
 //   data[outer * s_outer + i * s_axis + x0 + c].
-// Input: Lin values (compact, placed at wrap_pos) or all n; output: all n or
-// Lout compact values picked at wrap_pos.
+// Input: Lin entries (compact, at their FFT positions) or all n; output: all
+// n or the Lout compact entries.
 struct ColArgs {
     void *data;
     const void *tw;
@@ -284,37 +321,38 @@ struct ColArgs {
     RadixList rl;
 };
 
+constexpr int kColThreads = 512;
+
 template <typename T, bool FWD>
-__global__ void __launch_bounds__(kFftThreads) fft_cols_kernel(ColArgs a) {
+__global__ void __launch_bounds__(kColThreads) fft_cols_kernel(ColArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c_t<T> *buf = reinterpret_cast<c_t<T> *>(smem_raw);
-    const int tid = threadIdx.x;
     const int n = a.n, C = a.C;
-    const int ls = n + 1;   // padded line stride: columns land in different banks
+    const int ls = n + 1;   // padded line stride
     const int x0 = blockIdx.x * C;
     const int nc = min(C, a.ncols - x0);
     c_t<T> *data = (c_t<T> *)a.data + (int64_t)blockIdx.y * a.s_outer + x0;
-
-    if (a.Lin < n) {
-        for (int idx = tid; idx < C * ls; idx += kFftThreads) buf[idx] = cmk<T>(0, 0);
-        __syncthreads();
-    }
-    for (int idx = tid; idx < a.Lin * C; idx += kFftThreads) {
-        const int i = idx / C, c = idx - i * C;
-        if (c < nc) {
-            const int pos = a.Lin < n ? wrap_pos(i, a.Lin, n) : i;
-            buf[c * ls + pos] = data[(int64_t)i * a.s_axis + c];
+    const int Lin = a.Lin, Lout = a.Lout;
+    const int64_t sa = a.s_axis;
+    auto ld = [&](int c, int pos) -> c_t<T> {
+        if (c >= nc) return cmk<T>(0, 0);
+        int i = pos;
+        if (Lin < n) {
+            i = compact_of(pos, Lin, n);
+            if (i < 0) return cmk<T>(0, 0);
         }
-    }
-    __syncthreads();
-    stockham_lines<T, 32, FWD>(buf, ls, C, n, a.rl, (const c_t<T> *)a.tw, tid);
-    for (int idx = tid; idx < a.Lout * C; idx += kFftThreads) {
-        const int o = idx / C, c = idx - o * C;
-        if (c < nc) {
-            const int pos = a.Lout < n ? wrap_pos(o, a.Lout, n) : o;
-            data[(int64_t)o * a.s_axis + c] = buf[c * ls + pos];
+        return data[(int64_t)i * sa + c];
+    };
+    auto st = [&](int c, int pos, c_t<T> v) {
+        if (c >= nc) return;
+        int o = pos;
+        if (Lout < n) {
+            o = compact_of(pos, Lout, n);
+            if (o < 0) return;
         }
-    }
+        data[(int64_t)o * sa + c] = v;
+    };
+    fft_lines<T, 16, kColThreads, FWD, true>(buf, ls, C, n, a.rl, (const c_t<T> *)a.tw, ld, st);
 }
 
 // ------------------------------------------------------------ launchers ----
@@ -329,14 +367,14 @@ static RadixList radix_list(const FftAxisPlan &f) {
 }
 
 // Largest number of lines such that every stage fits VMAX values per thread.
-static int lines_fit(const FftAxisPlan &f, int vmax, int cap) {
+static int lines_fit(const FftAxisPlan &f, int vmax, int cap, int nthreads) {
     int best = 1;
     for (int L = 1; L <= cap; ++L) {
         bool ok = true;
         for (int s = 0; s < f.nrad; ++s) {
             const int R = f.radix[s];
             const int NB = L * (f.n / R);
-            const int per = (NB + kFftThreads - 1) / kFftThreads;
+            const int per = (NB + nthreads - 1) / nthreads;
             if (per > vmax / R) { ok = false; break; }
         }
         if (ok) best = L;
@@ -364,14 +402,14 @@ static int rows_pass(nfft3_plan_impl *p, int mode, const void *in, void *out, in
     a.deriv = deriv;
     a.rl = radix_list(f);
     const int cap = std::max(1, (int)(32768 / (f.n * sizeof(c_t<T>))));
-    a.lpw = lines_fit(f, 16, std::max(1, std::min(cap, 64)));
+    a.lpw = lines_fit(f, 16, std::max(1, std::min(cap, 64)), kRowThreads);
     const int64_t nrows = p->N[0] * p->N[1];
     const int64_t nblk = (nrows + a.lpw - 1) / a.lpw;
     const size_t lds = (size_t)a.lpw * f.n * sizeof(c_t<T>);
     if (mode == 0)
-        hipLaunchKernelGGL((fft_rows_kernel<T, 0>), dim3((unsigned)nblk), dim3(kFftThreads), lds, p->stream, a);
+        hipLaunchKernelGGL((fft_rows_kernel<T, 0>), dim3((unsigned)nblk), dim3(kRowThreads), lds, p->stream, a);
     else
-        hipLaunchKernelGGL((fft_rows_kernel<T, 1>), dim3((unsigned)nblk), dim3(kFftThreads), lds, p->stream, a);
+        hipLaunchKernelGGL((fft_rows_kernel<T, 1>), dim3((unsigned)nblk), dim3(kRowThreads), lds, p->stream, a);
     NFFT3_LAUNCH_CHECK("fft_rows_kernel");
     return NFFT3_OK;
 }
@@ -393,17 +431,17 @@ static int cols_pass(nfft3_plan_impl *p, int axis, bool fwd, int Lin, int Lout, 
     // 128-byte column segments, bounded by LDS (64 KiB) and registers
     int C = (int)(128 / sizeof(c_t<T>));
     while (C > 1 && (size_t)C * (f.n + 1) * sizeof(c_t<T>) > kColsLdsMax) C /= 2;
-    C = std::min(C, lines_fit(f, 32, C));
+    C = std::min(C, lines_fit(f, 16, C, kColThreads));
     C = std::min<int>(C, a.ncols);
     a.C = C;
     dim3 grid((unsigned)((a.ncols + C - 1) / C), (unsigned)n_outer);
     const size_t lds = (size_t)C * (f.n + 1) * sizeof(c_t<T>);
     if (fwd) {
         allow_lds((const void *)fft_cols_kernel<T, true>, lds);
-        hipLaunchKernelGGL((fft_cols_kernel<T, true>), grid, dim3(kFftThreads), lds, p->stream, a);
+        hipLaunchKernelGGL((fft_cols_kernel<T, true>), grid, dim3(kColThreads), lds, p->stream, a);
     } else {
         allow_lds((const void *)fft_cols_kernel<T, false>, lds);
-        hipLaunchKernelGGL((fft_cols_kernel<T, false>), grid, dim3(kFftThreads), lds, p->stream, a);
+        hipLaunchKernelGGL((fft_cols_kernel<T, false>), grid, dim3(kColThreads), lds, p->stream, a);
     }
     NFFT3_LAUNCH_CHECK("fft_cols_kernel");
     return NFFT3_OK;

@@ -61,8 +61,9 @@ struct FftAxisPlan {
 };
 
 // Points are sorted by (tile, z-cell); a tile is By x Bx cells of the (y, x)
-// plane.  Work items for the window-sum kernels are at most kItemPts points of
-// one tile column spanning at most kItemZ z-cells.
+// plane.  Work items for the window-sum kernels are at most Subproblems::maxpts
+// points (a multiple of the kItemPts threads of a workgroup) of one tile
+// column spanning at most kItemZ z-cells.
 constexpr int kItemPts = 256;
 constexpr int kItemZ = 64;
 constexpr int kMaxPlane = 12 * kItemPts;   // staged plane elements per workgroup
@@ -79,6 +80,7 @@ struct Bins {
 };
 
 struct Subproblems {
+    int maxpts = 1024;        // points per item at most (points per thread x 256)
     int64_t count = 0;        // number of work items
     int4 *items = nullptr;    // (tile, first sorted index, end sorted index, 0) (device)
     int64_t cap = 0;

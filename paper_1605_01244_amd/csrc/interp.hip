@@ -97,6 +97,7 @@ struct PSArgs {
     int deg;
     int n0, n1, n2;
     int By, Bx, ntx;
+    int pad8;               // pad the plane row stride to 8 mod 16 elements
 };
 
 // Per-workgroup setup shared by the three kernels.
@@ -106,26 +107,42 @@ struct PSItem {
     bool active;
     int zbeg, nplanes;   // planes zbeg .. zbeg+nplanes-1 (unwrapped)
     int PY, PX, psz;
+    int PXp;             // LDS row stride of the plane (padded)
 };
 
-__device__ __forceinline__ PSItem ps_item(const PSArgs &a, int m) {
+// Work-item order: the hardware hands consecutive workgroups to the 8 XCDs in
+// turn; map them so that each XCD walks a contiguous run of items (consecutive
+// items of one tile column share 2m-1 halo planes, which then hit its L2).
+__device__ __forceinline__ int xcd_item(int b, int G) {
+    const int q = G / 8, r = G % 8;
+    const int x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Geometry of the points [lo, hi) (sorted indices) of tile `tile`.
+__device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int lo, int hi) {
     PSItem it;
-    const int4 item = a.items[blockIdx.x];
-    const int ty = item.x / a.ntx, tx = item.x - ty * a.ntx;
+    const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
     it.y0 = ty * a.By;
     it.x0 = tx * a.Bx;
-    it.p = item.y + threadIdx.x;
-    it.active = it.p < item.z;
-    // points of an item are sorted by z-cell: the first and last give the range
+    it.p = lo + threadIdx.x;
+    it.active = it.p < hi;
+    // points are sorted by z-cell: the first and last give the range
     float dummy;
-    const int zmin = cell_frac<float>(a.xs[3 * item.y], a.n0, dummy);
-    const int zmax = cell_frac<float>(a.xs[3 * (item.z - 1)], a.n0, dummy);
+    const int zmin = cell_frac<float>(a.xs[3 * lo], a.n0, dummy);
+    const int zmax = cell_frac<float>(a.xs[3 * (hi - 1)], a.n0, dummy);
     it.zbeg = zmin - m + 1;
     it.nplanes = zmax - zmin + 2 * m;
     it.PY = a.By + 2 * m - 1;
     it.PX = a.Bx + 2 * m - 1;
     it.psz = it.PY * it.PX;
+    it.PXp = a.pad8 ? it.PX + ((8 - it.PX % 16) + 16) % 16 : it.PX;
     return it;
+}
+
+__device__ __forceinline__ PSItem ps_item(const PSArgs &a, int m, int4 &item) {
+    item = a.items[xcd_item(blockIdx.x, gridDim.x)];
+    return ps_range(a, m, item.x, item.y, item.z);
 }
 
 // Offsets (within a plane) of the elements this thread stages.
@@ -169,12 +186,49 @@ __device__ __forceinline__ void ps_store(c_t<T> *buf, const PSItem &it, const T 
     }
 }
 
+// LDS bank spreading.  Lane l of a wavefront natively takes sorted point
+// base + 64 w + l (z-adjacent points, so the wave is active on the same
+// planes).  The stencil read of an instruction is, per lane, plane element
+// (row + yo) * PX + (col + xo): the bank a lane hits is fixed by its class
+// c = (yo * PX + xo) mod 16.  Sorting the wave's 64 points by class and
+// dealing them out transposed (sorted position p -> lane 16 (p mod 4) + p/4)
+// gives each 16-lane (and 8-lane) issue group distinct classes when the
+// classes are balanced, instead of random ones.  Returns the lane-local index
+// (0..255) of the point this thread takes.
+__device__ __forceinline__ int wave_spread(const PSArgs &a, const PSItem &it, int base, int end) {
+    const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+    const int pk = base + threadIdx.x;
+    const bool valid = pk < end;
+    int c = 16;                     // invalid lanes sort last
+    if (valid) {
+        float f;
+        const int yc = cell_frac<float>(a.xs[3 * pk + 1], a.n1, f);
+        const int xc = cell_frac<float>(a.xs[3 * pk + 2], a.n2, f);
+        c = ((yc - it.y0) * it.PX + (xc - it.x0)) & 15;
+    }
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int pos = 0, rank = 0;
+#pragma unroll
+    for (int q = 0; q <= 16; ++q) {
+        const uint64_t mq = __ballot(c == q);
+        if (q < c) pos += __popcll(mq);
+        if (q == c) rank = __popcll(mq & below);
+    }
+    pos += rank;                    // position in class-sorted order, 0..63
+    const int tgt = 16 * (pos & 3) + (pos >> 2);
+    const int src = __builtin_amdgcn_ds_permute(tgt << 2, lane);
+    return wbase + src;
+}
+
 // ------------------------------------------------------------ interp ----
-template <typename T, int W>
+// Point slot k of thread t is sorted index item.y + k*256 + t: each slot's
+// wavefronts hold z-adjacent points, so they are active on the same planes.
+template <typename T, int W, int PPT>
 __global__ void __launch_bounds__(kPsThreads) interp_ps_kernel(PSArgs a) {
     constexpr int m = W / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const PSItem it = ps_item(a, m);
+    int4 item;
+    const PSItem it = ps_item(a, m, item);
     c_t<T> *buf0 = reinterpret_cast<c_t<T> *>(smem_raw);
     c_t<T> *buf1 = buf0 + it.psz;
     T *scoef = reinterpret_cast<T *>(buf1 + it.psz);
@@ -182,21 +236,30 @@ __global__ void __launch_bounds__(kPsThreads) interp_ps_kernel(PSArgs a) {
     const int nc = W * (a.deg + 1);
     for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
 
-    T w1[W], w2[W];
-    T f0 = 0;
-    int zc = 0, yo = 0, xo = 0;
-    if (it.active) {
-        const double *xp = a.xs + 3 * it.p;
-        T f1, f2;
-        zc = cell_frac<T>(xp[0], a.n0, f0);
-        const int yc = cell_frac<T>(xp[1], a.n1, f1);
-        const int xc = cell_frac<T>(xp[2], a.n2, f2);
-        yo = yc - it.y0;
-        xo = xc - it.x0;
-        window_weights<T, W>(f1, coef, a.deg, w1);
-        window_weights<T, W>(f2, coef, a.deg, w2);
+    T w1[PPT][W], w2[PPT][W];
+    T f0[PPT], ar[PPT], ai[PPT];
+    int zlo[PPT], pofs[PPT], pidx[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int pk = item.y + k * kPsThreads + wave_spread(a, it, item.y + k * kPsThreads, item.z);
+        pidx[k] = pk;
+        ar[k] = 0;
+        ai[k] = 0;
+        zlo[k] = -4 * W;     // never active
+        pofs[k] = -1;
+        f0[k] = 0;
+        if (pk < item.z) {
+            const double *xp = a.xs + 3 * pk;
+            T f1, f2;
+            const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
+            const int yc = cell_frac<T>(xp[1], a.n1, f1);
+            const int xc = cell_frac<T>(xp[2], a.n2, f2);
+            pofs[k] = (yc - it.y0) * it.PX + (xc - it.x0);
+            zlo[k] = zc - m + 1 - it.zbeg;      // first plane index of the stencil
+            window_weights<T, W>(f1, coef, a.deg, w1[k]);
+            window_weights<T, W>(f2, coef, a.deg, w2[k]);
+        }
     }
-    const int zlo = zc - m + 1 - it.zbeg;   // first plane index of this point's stencil
 
     int off[kMaxPF];
     ps_offsets(a, it, m, off);
@@ -207,36 +270,42 @@ __global__ void __launch_bounds__(kPsThreads) interp_ps_kernel(PSArgs a) {
     ps_store<T>(buf0, it, rr, ri);
     __syncthreads();
 
-    T ar = 0, ai = 0;
     for (int i = 0; i < it.nplanes; ++i) {
         const bool more = i + 1 < it.nplanes;
         if (more) ps_fetch<T>(grid, it, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, rr, ri);
         const c_t<T> *pl = (i & 1) ? buf1 : buf0;
-        const int r0 = i - zlo;
-        if (it.active && r0 >= 0 && r0 < W) {
-            const T w0 = piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0);
-            T sr = 0, si = 0;
-            const c_t<T> *base = pl + yo * it.PX + xo;
-#pragma unroll 2
-            for (int r1 = 0; r1 < W; ++r1) {
-                const c_t<T> *row = base + r1 * it.PX;
-                T cr = 0, ci = 0;
 #pragma unroll
-                for (int r2 = 0; r2 < W; ++r2) {
-                    const c_t<T> g = row[r2];
-                    cr += w2[r2] * g.x;
-                    ci += w2[r2] * g.y;
+        for (int k = 0; k < PPT; ++k) {
+            const int r0 = i - zlo[k];
+            if (r0 >= 0 && r0 < W) {
+                const T w0 = piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
+                T sr = 0, si = 0;
+                const c_t<T> *base = pl + pofs[k];
+#pragma unroll
+                for (int r1 = 0; r1 < W; ++r1) {
+                    const c_t<T> *row = base + r1 * it.PX;
+                    T cr = 0, ci = 0;
+#pragma unroll
+                    for (int r2 = 0; r2 < W; ++r2) {
+                        const c_t<T> g = row[r2];
+                        cr += w2[k][r2] * g.x;
+                        ci += w2[k][r2] * g.y;
+                    }
+                    sr += w1[k][r1] * cr;
+                    si += w1[k][r1] * ci;
                 }
-                sr += w1[r1] * cr;
-                si += w1[r1] * ci;
+                ar[k] += w0 * sr;
+                ai[k] += w0 * si;
             }
-            ar += w0 * sr;
-            ai += w0 * si;
         }
         if (more) ps_store<T>((i & 1) ? buf0 : buf1, it, rr, ri);
         __syncthreads();
     }
-    if (it.active) ((c_t<T> *)a.out)[a.perm[it.p]] = cmk<T>(ar, ai);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int pk = pidx[k];
+        if (pk < item.z) ((c_t<T> *)a.out)[a.perm[pk]] = cmk<T>(ar[k], ai[k]);
+    }
 }
 
 // ------------------------------------------------------------- grad ----
@@ -244,7 +313,11 @@ template <typename T, int W>
 __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
     constexpr int m = W / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const PSItem it = ps_item(a, m);
+    const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
+    // items may hold more points than threads: take them 256 at a time
+    for (int lo = item.y; lo < item.z; lo += kPsThreads) {
+    __syncthreads();
+    const PSItem it = ps_range(a, m, item.x, lo, min(item.z, lo + kPsThreads));
     c_t<T> *buf0 = reinterpret_cast<c_t<T> *>(smem_raw);
     c_t<T> *buf1 = buf0 + it.psz;
     T *scoef = reinterpret_cast<T *>(buf1 + it.psz);
@@ -319,6 +392,7 @@ __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
         gx[1] = (double)a.n1 * ((double)g.x * (double)D1r + (double)g.y * (double)D1i);
         gx[2] = (double)a.n2 * ((double)g.x * (double)D2r + (double)g.y * (double)D2i);
     }
+    }
 }
 
 // ------------------------------------------------------------ spread ----
@@ -326,7 +400,10 @@ template <typename T, int W>
 __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     constexpr int m = W / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const PSItem it = ps_item(a, m);
+    const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
+    for (int lo = item.y; lo < item.z; lo += kPsThreads) {
+    __syncthreads();
+    const PSItem it = ps_range(a, m, item.x, lo, min(item.z, lo + kPsThreads));
     c_t<T> *acc = reinterpret_cast<c_t<T> *>(smem_raw);
     T *scoef = reinterpret_cast<T *>(acc + it.psz);
     const T *coef = (const T *)a.coef;
@@ -390,6 +467,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         }
         __syncthreads();
     }
+    }
 }
 
 __global__ void zero_kernel(float4 *p, int64_t count) {
@@ -424,6 +502,7 @@ static PSArgs ps_args(nfft3_plan_impl *p) {
     a.By = p->bins.By;
     a.Bx = p->bins.Bx;
     a.ntx = p->bins.ntx;
+    a.pad8 = 0;
     return a;
 }
 
@@ -433,17 +512,27 @@ static size_t ps_lds(nfft3_plan_impl *p, int nbuf) {
     return nbuf * psz * p->elt + (size_t)W * (p->deg + 1) * (p->elt / 2);
 }
 
-template <typename T, int W>
-static int interp_w(nfft3_plan_impl *p, const void *grid, void *f) {
-    if (p->M == 0 || p->sub.count == 0) return NFFT3_OK;
+template <typename T, int W, int PPT>
+static int interp_ppt(nfft3_plan_impl *p, const void *grid, void *f) {
     PSArgs a = ps_args(p);
     a.grid = grid;
     a.out = f;
     const size_t lds = ps_lds(p, 2);
-    allow_lds((const void *)interp_ps_kernel<T, W>, lds);
-    hipLaunchKernelGGL((interp_ps_kernel<T, W>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds, p->stream, a);
+    allow_lds((const void *)interp_ps_kernel<T, W, PPT>, lds);
+    hipLaunchKernelGGL((interp_ps_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
+                       p->stream, a);
     NFFT3_LAUNCH_CHECK("interp_ps_kernel");
     return NFFT3_OK;
+}
+
+template <typename T, int W>
+static int interp_w(nfft3_plan_impl *p, const void *grid, void *f) {
+    if (p->M == 0 || p->sub.count == 0) return NFFT3_OK;
+    switch (p->sub.maxpts / kPsThreads) {
+        case 1: return interp_ppt<T, W, 1>(p, grid, f);
+        case 2: return interp_ppt<T, W, 2>(p, grid, f);
+        default: return NFFT3_ERR_INVALID_ARG;
+    }
 }
 
 template <typename T, int W>

@@ -4,7 +4,7 @@
 // points with a counting sort (histogram -> exclusive scan -> scatter) by the
 // key (tile, z-cell), where a tile is a By x Bx block of cells in the (y, x)
 // plane and z (axis 0) varies fastest.  Each tile column is then cut into
-// work items of at most kItemPts points spanning at most kItemZ z-cells; a
+// work items of at most maxpts points spanning at most kItemZ z-cells; a
 // workgroup of the window-sum kernels takes one item and streams the z-planes
 // of its tile (plus the stencil halo) through LDS.
 #include "internal.h"
@@ -148,13 +148,13 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
 }
 
 // ---- work items: walk each tile column's z-cells (one thread per tile) ------
-// A new item starts when adding the next cell would exceed kItemPts points or
+// A new item starts when adding the next cell would exceed maxpts points or
 // the item would span more than kItemZ z-cells; a cell holding more than
-// kItemPts points becomes ceil(count/kItemPts) items of its own.  WRITE=false
+// maxpts points becomes ceil(count/maxpts) items of its own.  WRITE=false
 // counts the items of each tile, WRITE=true emits (tile, p_lo, p_hi, 0).
 template <bool WRITE>
 __global__ void __launch_bounds__(256)
-items_kernel(const int *__restrict__ counts, const int *__restrict__ offsets, int ntiles, int n0,
+items_kernel(const int *__restrict__ counts, const int *__restrict__ offsets, int ntiles, int n0, int maxpts,
              int *__restrict__ item_count, const int *__restrict__ item_offset, int4 *__restrict__ items) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
@@ -166,14 +166,14 @@ items_kernel(const int *__restrict__ counts, const int *__restrict__ offsets, in
     for (int z = 0; z < n0; ++z) {
         const int c = cnt[z];
         if (c == 0) continue;
-        if (cur > 0 && (cur + c > kItemPts || z - z_start >= kItemZ)) {
+        if (cur > 0 && (cur + c > maxpts || z - z_start >= kItemZ)) {
             if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
             ++k;
             cur = 0;
         }
-        if (c > kItemPts) {   // a dense cell on its own
-            for (int s = 0; s < c; s += kItemPts) {
-                if (WRITE) items[w + k] = make_int4(tile, off[z] + s, off[z] + min(c, s + kItemPts), 0);
+        if (c > maxpts) {     // a dense cell on its own
+            for (int s = 0; s < c; s += maxpts) {
+                if (WRITE) items[w + k] = make_int4(tile, off[z] + s, off[z] + min(c, s + maxpts), 0);
                 ++k;
             }
             continue;
@@ -217,7 +217,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     // work items
     const unsigned tb = (unsigned)((ntiles + 255) / 256);
     hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(256), 0, s, p->bins.counts, p->bins.offsets, ntiles,
-                       g.in0, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr);
+                       g.in0, p->sub.maxpts, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr);
     NFFT3_LAUNCH_CHECK("items_kernel");
     rc = exclusive_scan(s, p->bins.tile_items, p->bins.tile_item_off, p->bins.scratch, ntiles);
     if (rc) return rc;
@@ -235,7 +235,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     p->sub.count = nitems;
     if (nitems > 0) {
         hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(256), 0, s, p->bins.counts, p->bins.offsets, ntiles,
-                           g.in0, (int *)nullptr, (const int *)p->bins.tile_item_off, p->sub.items);
+                           g.in0, p->sub.maxpts, (int *)nullptr, (const int *)p->bins.tile_item_off, p->sub.items);
         NFFT3_LAUNCH_CHECK("items_kernel");
     }
     return NFFT3_OK;
