@@ -64,8 +64,7 @@ enum nfft3_status {
     NFFT3_ERR_NO_POINTS = -4,   /* trafo/adjoint/grad before nfft3_set_points    */
     NFFT3_ERR_NONFINITE = -5,   /* a point coordinate is NaN or infinite         */
     NFFT3_ERR_HIP = -6,         /* HIP runtime error (see nfft3_last_hip_error)  */
-    NFFT3_ERR_NULL = -7,        /* NULL plan or NULL required pointer            */
-    NFFT3_ERR_TIMEOUT = -8      /* batched launch: a stage wait hit its spin limit */
+    NFFT3_ERR_NULL = -7         /* NULL plan or NULL required pointer            */
 };
 
 /* Create a plan for coefficient sizes N[0..2] (host array).
@@ -125,17 +124,19 @@ int nfft3_grad_points(nfft3_plan_t p, const void *fhat_dev, const void *G_dev, d
 int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int deriv_mask);
 
 /* Batched type-2 evaluation of T independent plans (own N, own points, same
- * dtype, sigma and m) in ONE persistent kernel launch.  For plan t,
- * fhat_dev[t] holds its coefficients and out_dev[t] receives
- * (1 + popcount(deriv_mask)) blocks of M_t values as in nfft3_trafo_fields.
- * fhat_dev / out_dev are host arrays of T device pointers.  Work is enqueued
- * on plans[0]'s stream.  The plans must be distinct; each keeps one grid per
+ * dtype, sigma and m, with m <= 8): the time snapshots and derivative fields
+ * of a vortex-tracking workload evaluated together.  For plan t, fhat_dev[t]
+ * holds its coefficients and out_dev[t] receives (1 + popcount(deriv_mask))
+ * blocks of M_t values as in nfft3_trafo_fields.  fhat_dev / out_dev are host
+ * arrays of T device pointers; plans is a host array of T distinct plans.
+ * The whole batch runs as four kernel launches, one per stage (row pass,
+ * column pass axis 1, column pass axis 0, window sums), each covering the
+ * work items of every (plan, field) pair.  Each plan keeps one grid per
  * evaluated field, allocated on its first batched call with a given mask.
- * Returns NFFT3_ERR_TIMEOUT if a stage wait exceeded the spin limit set by
- * nfft3_batch_set_spin_limit (every wave still exits; outputs are invalid). */
+ * Work is enqueued on plans[0]'s stream; the call returns after it finished
+ * (the launch descriptors are staged from host memory). */
 int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
                       void *const *out_dev, int deriv_mask);
-int nfft3_batch_set_spin_limit(int64_t spins);   /* <= 0 restores the default (no practical limit) */
 
 /* Release every buffer of the plan.  NULL is a no-op. */
 int nfft3_destroy(nfft3_plan_t p);

@@ -26,8 +26,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 from ._lib import NFFT3_C64, NFFT3_C128, NFFT3Error, check, lib
 
-__all__ = ["Plan", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error",
-           "set_batch_spin_limit"]
+__all__ = ["Plan", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error"]
 
 _DT = {torch.complex64: NFFT3_C64, torch.complex128: NFFT3_C128}
 
@@ -176,8 +175,9 @@ class Plan:
 
 
 def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0):
-    """Evaluate every plan's coefficients (and derivative fields) in one
-    batched launch.  Returns a list of (1 + popcount(mask), M_t) tensors."""
+    """Evaluate every plan's coefficients (and derivative fields) together:
+    one launch per stage over all (plan, field) pairs.  Returns a list of
+    (1 + popcount(mask), M_t) tensors."""
     T = len(plans)
     if T != len(fhats):
         raise ValueError("one coefficient array per plan")
@@ -192,10 +192,6 @@ def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask
     O = (ctypes.c_void_p * T)(*[o.data_ptr() for o in outs])
     check(lib.nfft3_batch_trafo(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo")
     return outs
-
-
-def set_batch_spin_limit(spins: int) -> None:
-    check(lib.nfft3_batch_set_spin_limit(int(spins)), "nfft3_batch_set_spin_limit")
 
 
 class _Type2(torch.autograd.Function):

@@ -24,7 +24,6 @@ STATUS = {
     -5: "NFFT3_ERR_NONFINITE",
     -6: "NFFT3_ERR_HIP",
     -7: "NFFT3_ERR_NULL",
-    -8: "NFFT3_ERR_TIMEOUT",
 }
 
 
@@ -56,7 +55,6 @@ def _load() -> ctypes.CDLL:
         "nfft3_grad_points": ([vp, vp, vp, vp], ci),
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),
         "nfft3_batch_trafo": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
-        "nfft3_batch_set_spin_limit": ([i64], ci),
         "nfft3_destroy": ([vp], ci),
         "nfft3_strerror": ([ci], ctypes.c_char_p),
         "nfft3_last_hip_error": ([], ctypes.c_char_p),

@@ -401,7 +401,8 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat,
         if (!plans[t]->have_points) return NFFT3_ERR_NO_POINTS;
         if (plans[t]->M > 0 && !out[t]) return NFFT3_ERR_NULL;
         if (plans[t]->dtype != plans[0]->dtype) return NFFT3_ERR_DTYPE;
-        if (plans[t]->m != plans[0]->m || plans[t]->sigma != plans[0]->sigma) return NFFT3_ERR_INVALID_ARG;
+        if (plans[t]->m != plans[0]->m || plans[t]->sigma != plans[0]->sigma || plans[t]->m > 8)
+            return NFFT3_ERR_INVALID_ARG;
         for (int u = 0; u < t; ++u)
             if (plans[u] == plans[t]) return NFFT3_ERR_INVALID_ARG;
     }
@@ -419,7 +420,6 @@ const char *nfft3_strerror(int code) {
         case NFFT3_ERR_NONFINITE: return "non-finite point coordinate";
         case NFFT3_ERR_HIP: return "HIP runtime error";
         case NFFT3_ERR_NULL: return "NULL plan or pointer";
-        case NFFT3_ERR_TIMEOUT: return "batched launch: stage wait exceeded the spin limit";
         default: return "unknown status";
     }
 }
