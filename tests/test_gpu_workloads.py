@@ -1,0 +1,157 @@
+"""Full-size workloads on the GPU, checked on sampled outputs against the
+direct-sum oracle (which is too slow for every output at these sizes).
+
+* vortex pair: 128^3 coefficients of a two-line vortex field, 128^3 points on
+  a fine grid in a 1/16-wide sub-box around the closest approach, FP64 m = 8;
+  plus the interpolation property at the sub-box points that coincide with
+  coarse nodes (the series reproduces the sampled field there, Sec. 2).
+* N = 256^3, M = 1e7 (half uniform, half in 16 clusters), FP32 m = 4 and
+  FP64 m = 8 on the same inputs, in the launch configuration bench.py times.
+* 64 coefficient sets of N in {64, 96, 128}^3 with lognormal point counts,
+  each with its three derivative fields, batched; batched = sequential and
+  sampled outputs vs the oracle.
+* N = 128^3, M = 1e6 clustered points, autograd backward in both forms:
+  coefficient gradient vs the brute-force adjoint sum on a 1e3-point run,
+  point gradient vs the oracle's derivative sum on sampled points.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_common import log, rel, to_dev, tol, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nf():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1605_01244_amd as mod
+    return mod
+
+
+def _free():
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_vortex_pair_subbox(nf):
+    fhat, pts, mask, psi = workloads.vortex_subbox_case(128, 128)
+    M = pts.shape[0]
+    log(f"vortex pair N=128^3 M={M} FP64 m=8")
+    plan = nf.Plan(fhat.shape, m=8, dtype=torch_dtype("c128"), device="cuda:0")
+    plan.set_points(to_dev(pts))
+    f = plan.trafo(to_dev(fhat, "c128")).cpu().numpy()
+    sample = workloads.sample_indices(M, 4000, 202)
+    ref = oracle.ndft_trafo(fhat, pts[sample])
+    l2, li = rel(f[sample], ref)
+    log(f"  sampled rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    assert l2 <= tol(8, 2.0, "c128") and li <= tol(8, 2.0, "c128")
+    # interpolation: at coarse nodes the series returns the sampled field
+    on = np.flatnonzero(mask)
+    assert on.size == 512
+    idx = workloads.coarse_index_of(pts[on], 128)
+    l2, li = rel(f[on], psi[idx[:, 0], idx[:, 1], idx[:, 2]])
+    log(f"  coarse-node interpolation rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    assert l2 <= tol(8, 2.0, "c128") and li <= tol(8, 2.0, "c128"), (l2, li)
+    plan.close()
+    _free()
+
+
+@pytest.fixture(scope="module")
+def powerlaw_case():
+    return workloads.powerlaw_mixed_case(256, 10_000_000)
+
+
+@pytest.mark.parametrize("dtype,m", [("c64", 4), ("c128", 8)])
+def test_powerlaw_256_1e7(nf, powerlaw_case, dtype, m):
+    fhat, x = powerlaw_case
+    log(f"N=256^3 M=1e7 {dtype} m={m}")
+    plan = nf.Plan(fhat.shape, m=m, dtype=torch_dtype(dtype), device="cuda:0")
+    plan.set_points(to_dev(x))
+    f = plan.trafo(to_dev(fhat, dtype))
+    sample = workloads.sample_indices(x.shape[0], 10_000, 306)[:600]
+    import torch
+    got = f[torch.from_numpy(sample).to(f.device)].cpu().numpy()
+    ref = oracle.ndft_trafo(fhat, x[sample])
+    l2, li = rel(got, ref)
+    log(f"  sampled rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    gate = 1e-12 if dtype == "c128" else 2e-6
+    assert l2 <= gate and li <= gate
+    # every output is finite and the output order is the caller's
+    assert torch.isfinite(torch.view_as_real(f)).all()
+    plan.close()
+    del f
+    _free()
+
+
+@pytest.mark.parametrize("dtype,m", [("c64", 4), ("c128", 8)])
+def test_batched_64_sets_with_derivative_fields(nf, dtype, m):
+    import torch
+    sets = workloads.batched_sets(64)
+    log(f"batched 64 sets {dtype} m={m}: M total {sum(s[2].shape[0] for s in sets)}")
+    plans, fh = [], []
+    for N, f, x in sets:
+        p = nf.Plan((N, N, N), m=m, dtype=torch_dtype(dtype), device="cuda:0")
+        p.set_points(to_dev(x))
+        plans.append(p)
+        fh.append(to_dev(f, dtype))
+    outs = nf.batch_trafo(plans, fh, 7)
+    torch.cuda.synchronize()
+    for t in (0, 1, 17, 40, 63):
+        seq = plans[t].trafo_fields(fh[t], 7)
+        assert torch.equal(outs[t], seq), t
+    gate = tol(m, 2.0, dtype)
+    worst = 0.0
+    for t, (N, f, x) in enumerate(sets):
+        s = workloads.sample_indices(x.shape[0], 12, 600 + t)
+        got = outs[t][:, torch.from_numpy(s).to(outs[t].device)].cpu().numpy()
+        ref0 = oracle.ndft_trafo(f, x[s])
+        D = oracle.ndft_grad(f, x[s])
+        for i, ref in enumerate([ref0, D[:, 0], D[:, 1], D[:, 2]]):
+            l2, li = rel(got[i], ref)
+            worst = max(worst, l2, li)
+    log(f"  worst sampled relative error {worst:.2e}")
+    assert worst <= gate
+    for p in plans:
+        p.close()
+    del outs
+    _free()
+
+
+@pytest.mark.parametrize("dtype,m", [("c128", 8), ("c64", 4)])
+def test_differentiation_128_1e6(nf, dtype, m):
+    import torch
+    fhat, x, w = workloads.clustered_grad_case(128, 1_000_000)
+    log(f"autograd N=128^3 M=1e6 {dtype} m={m}")
+    plan = nf.Plan(fhat.shape, m=m, dtype=torch_dtype(dtype), device="cuda:0")
+    fh = to_dev(fhat, dtype).requires_grad_(True)
+    xd = to_dev(x).requires_grad_(True)
+    f = nf.type2(fh, xd, plan)
+    L = (torch.conj(to_dev(w, dtype)) * f).real.sum()
+    L.backward()
+    # point gradient on sampled points vs the oracle's derivative sum
+    s = workloads.sample_indices(x.shape[0], 300, 705)
+    gx = xd.grad[torch.from_numpy(s).to(xd.device)].cpu().numpy()
+    D = oracle.ndft_grad(fhat, x[s])
+    ref = (np.conj(w[s])[:, None] * D).real
+    l2, li = rel(gx, ref)
+    log(f"  grad_x rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    assert l2 <= 10 * tol(m, 2.0, dtype) and li <= 10 * tol(m, 2.0, dtype)
+    assert torch.isfinite(fh.grad.real).all() and torch.isfinite(fh.grad.imag).all()
+    # coefficient gradient: adjoint on a 1e3-point run vs the brute-force adjoint sum
+    s2 = workloads.sample_indices(x.shape[0], 1000, 704)
+    plan.set_points(to_dev(x[s2]))
+    g = plan.adjoint(to_dev(w[s2], dtype)).cpu().numpy()
+    ref = oracle.ndft_adjoint(w[s2], x[s2], fhat.shape)
+    l2, li = rel(g, ref)
+    log(f"  adjoint (1e3 points) rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype)
+    plan.close()
+    _free()
