@@ -250,9 +250,9 @@ static int build_plan(nfft3_plan_impl *p) {
     p->deg = deg;
     int rc = f64 ? upload_real<double>(coef, &p->wcoef) : upload_real<float>(coef, &p->wcoef);
     if (rc) return rc;
-    // point tiles: the largest power of two <= 32 whose plane (tile + stencil
-    // halo) fits the window-sum kernels' staging (kMaxPlane elements)
-    int T = 32;
+    // point tiles: the largest power of two <= kMaxTile whose plane (tile +
+    // stencil halo) fits the window-sum kernels' staging (kMaxPlane elements)
+    int T = kMaxTile;
     while (T > 1 && (T + 2 * p->m - 1) * (T + 2 * p->m - 1) > kMaxPlane) T /= 2;
     p->bins.By = (int)std::min<int64_t>(T, p->n[1]);
     p->bins.Bx = (int)std::min<int64_t>(T, p->n[2]);

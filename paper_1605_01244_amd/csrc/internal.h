@@ -67,6 +67,7 @@ struct FftAxisPlan {
 constexpr int kItemPts = 256;
 constexpr int kItemZ = 64;
 constexpr int kMaxPlane = 12 * kItemPts;   // staged plane elements per workgroup
+constexpr int kMaxTile = 32;               // By, Bx never exceed this
 
 struct Bins {
     int By = 32, Bx = 32;     // tile size in cells (y, x)

@@ -59,20 +59,21 @@ __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
         window_weights_d<T, W>(f2, coef, a.deg, w2, d2);
     }
     const int zlo = zc - m + 1 - it.zbeg;
-    int off[kMaxPF];
-    ps_offsets(a, it, m, off);
+    constexpr int NF = ps_nf<W>();
+    int off[NF];
+    ps_offsets<NF>(a, it, m, off);
     const c_t<T> *grid = (const c_t<T> *)a.grid;
     const int64_t plane = (int64_t)a.n1 * a.n2;
-    T rr[kMaxPF], ri[kMaxPF];
-    ps_fetch<T>(grid, it, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, rr, ri);
-    ps_store<T>(buf0, it, rr, ri);
+    vec2_t<T> stage[NF];
+    ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
+    ps_store<T, NF>(buf0, it, stage);
     __syncthreads();
 
     // D0 = sum d0 w1 w2 g, D1 = sum w0 d1 w2 g, D2 = sum w0 w1 d2 g
     T D0r = 0, D0i = 0, D1r = 0, D1i = 0, D2r = 0, D2i = 0;
     for (int i = 0; i < it.nplanes; ++i) {
         const bool more = i + 1 < it.nplanes;
-        if (more) ps_fetch<T>(grid, it, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, rr, ri);
+        if (more) ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, stage);
         const c_t<T> *pl = (i & 1) ? buf1 : buf0;
         const int r0 = i - zlo;
         if (it.active && r0 >= 0 && r0 < W) {
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
             D1r += w0 * ur;  D1i += w0 * ui;
             D2r += w0 * tr;  D2i += w0 * ti;
         }
-        if (more) ps_store<T>((i & 1) ? buf0 : buf1, it, rr, ri);
+        if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, stage);
         __syncthreads();
     }
     if (it.active) {
@@ -147,8 +148,9 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         v = ((const c_t<T> *)a.vals)[a.perm[it.p]];
     }
     const int zlo = zc - m + 1 - it.zbeg;
-    int off[kMaxPF];
-    ps_offsets(a, it, m, off);
+    constexpr int NF = ps_nf<W>();
+    int off[NF];
+    ps_offsets<NF>(a, it, m, off);
     c_t<T> *grid = (c_t<T> *)a.grid_out;
     const int64_t plane = (int64_t)a.n1 * a.n2;
     __syncthreads();
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         // flush this plane to the grid and clear it
         const int64_t zoff = (int64_t)wrapi(it.zbeg + i, a.n0) * plane;
 #pragma unroll
-        for (int k = 0; k < kMaxPF; ++k) {
+        for (int k = 0; k < NF; ++k) {
             const int e = threadIdx.x + k * kPsThreads;
             if (e < it.psz) {
                 const c_t<T> s = acc[e];

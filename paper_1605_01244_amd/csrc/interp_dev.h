@@ -7,7 +7,16 @@
 namespace nfft3 {
 
 constexpr int kPsThreads = kItemPts;   // one point per thread
-constexpr int kMaxPF = kMaxPlane / kPsThreads;   // staged plane elements per thread
+
+// Staged plane elements per thread for window width W: the plane region is
+// at most (kMaxTile + W - 1)^2 elements.
+template <int W>
+constexpr int ps_nf() {
+    return ((kMaxTile + W - 1) * (kMaxTile + W - 1) + kPsThreads - 1) / kPsThreads;
+}
+
+template <typename T>
+using vec2_t = T __attribute__((ext_vector_type(2)));
 
 template <typename T, int W>
 __device__ __forceinline__ void window_weights(T f, const T *__restrict__ coef, int deg, T *w) {
@@ -130,10 +139,12 @@ __device__ __forceinline__ PSItem ps_item(const PSArgs &a, int m, int4 &item) {
     return ps_range(a, m, item.x, item.y, item.z);
 }
 
-// Offsets (within a plane) of the elements this thread stages.
+// Offsets (within a plane) of the elements this thread stages; slots past
+// the region point at element 0 so that every slot can be loaded.
+template <int NF>
 __device__ __forceinline__ void ps_offsets(const PSArgs &a, const PSItem &it, int m, int *off) {
 #pragma unroll
-    for (int k = 0; k < kMaxPF; ++k) {
+    for (int k = 0; k < NF; ++k) {
         const int e = threadIdx.x + k * kPsThreads;
         if (e < it.psz) {
             const int ly = e / it.PX, lx = e - ly * it.PX;
@@ -146,28 +157,25 @@ __device__ __forceinline__ void ps_offsets(const PSArgs &a, const PSItem &it, in
     }
 }
 
-// Staged values are kept as separate real/imaginary arrays: an array of the
-// HIP complex vector type is not promoted to registers for double.
-template <typename T>
-__device__ __forceinline__ void ps_fetch(const c_t<T> *__restrict__ grid, const PSItem &it, const int *off,
-                                         int64_t zoff, T *rr, T *ri) {
+// The loads are unconditional (no branch between them), so all NF are in
+// flight together and the wait falls at the LDS store after the plane's
+// compute; the values are held as native two-element vectors, which stay in
+// registers for both precisions.
+template <typename T, int NF>
+__device__ __forceinline__ void ps_fetch(const c_t<T> *__restrict__ grid, const int *off, int64_t zoff,
+                                         vec2_t<T> *v) {
+    const vec2_t<T> *g = reinterpret_cast<const vec2_t<T> *>(grid) + zoff;
 #pragma unroll
-    for (int k = 0; k < kMaxPF; ++k) {
-        const int e = threadIdx.x + k * kPsThreads;
-        if (e < it.psz) {
-            const c_t<T> g = grid[zoff + off[k]];
-            rr[k] = g.x;
-            ri[k] = g.y;
-        }
-    }
+    for (int k = 0; k < NF; ++k) v[k] = g[off[k]];
 }
 
-template <typename T>
-__device__ __forceinline__ void ps_store(c_t<T> *buf, const PSItem &it, const T *rr, const T *ri) {
+template <typename T, int NF>
+__device__ __forceinline__ void ps_store(c_t<T> *buf, const PSItem &it, const vec2_t<T> *v) {
+    vec2_t<T> *b = reinterpret_cast<vec2_t<T> *>(buf);
 #pragma unroll
-    for (int k = 0; k < kMaxPF; ++k) {
+    for (int k = 0; k < NF; ++k) {
         const int e = threadIdx.x + k * kPsThreads;
-        if (e < it.psz) buf[e] = cmk<T>(rr[k], ri[k]);
+        if (e < it.psz) b[e] = v[k];
     }
 }
 
@@ -245,18 +253,19 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
         }
     }
 
-    int off[kMaxPF];
-    ps_offsets(a, it, m, off);
+    constexpr int NF = ps_nf<W>();
+    int off[NF];
+    ps_offsets<NF>(a, it, m, off);
     const c_t<T> *grid = (const c_t<T> *)a.grid;
     const int64_t plane = (int64_t)a.n1 * a.n2;
-    T rr[kMaxPF], ri[kMaxPF];
-    ps_fetch<T>(grid, it, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, rr, ri);
-    ps_store<T>(buf0, it, rr, ri);
+    vec2_t<T> stage[NF];
+    ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
+    ps_store<T, NF>(buf0, it, stage);
     __syncthreads();
 
     for (int i = 0; i < it.nplanes; ++i) {
         const bool more = i + 1 < it.nplanes;
-        if (more) ps_fetch<T>(grid, it, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, rr, ri);
+        if (more) ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, stage);
         const c_t<T> *pl = (i & 1) ? buf1 : buf0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -282,7 +291,7 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
                 ai[k] += w0 * si;
             }
         }
-        if (more) ps_store<T>((i & 1) ? buf0 : buf1, it, rr, ri);
+        if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, stage);
         __syncthreads();
     }
 #pragma unroll
