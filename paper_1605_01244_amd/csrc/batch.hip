@@ -100,7 +100,8 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             b.rows = make_row_args<T>(p, fhat[t], grid, fields[f], kBRowThreads);
             b.c1 = make_col_args<T>(p, grid, 1, (int)p->N[1], (int)p->n[1], p->n[1] * p->n[2], kBColThreads, 16);
             b.c0 = make_col_args<T>(p, grid, 0, (int)p->N[0], (int)p->n[0], p->n[2], kBColThreads, 16);
-            b.ip = ps_args(p);
+            b.ip = interp_args(p);
+            if (!interp_layout_ok(p, b.ip)) return NFFT3_ERR_INVALID_ARG;
             b.ip.grid = grid;
             b.ip.out = (char *)out[t] + (size_t)f * p->M * p->elt;
             b.gx1 = col_grid_x(b.c1);
@@ -112,7 +113,7 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             lds[0] = std::max(lds[0], row_lds<T>(b.rows));
             lds[1] = std::max(lds[1], col_lds<T>(b.c1));
             lds[2] = std::max(lds[2], col_lds<T>(b.c0));
-            lds[3] = std::max(lds[3], ps_lds(p, 2));
+            lds[3] = std::max(lds[3], interp_lds(p, b.ip));
         }
     }
     // per-stage prefix tables of item counts: first[s][t], X + 1 entries each

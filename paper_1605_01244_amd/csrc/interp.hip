@@ -60,13 +60,13 @@ __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
     }
     const int zlo = zc - m + 1 - it.zbeg;
     constexpr int NF = ps_nf<W>();
-    int off[NF];
-    ps_offsets<NF>(a, it, m, off);
+    int off[NF], lidx[NF];
+    ps_offsets<NF>(a, it, m, off, lidx);
     const c_t<T> *grid = (const c_t<T> *)a.grid;
     const int64_t plane = (int64_t)a.n1 * a.n2;
     vec2_t<T> stage[NF];
     ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
-    ps_store<T, NF>(buf0, it, stage);
+    ps_store<T, NF>(buf0, it, lidx, stage);
     __syncthreads();
 
     // D0 = sum d0 w1 w2 g, D1 = sum w0 d1 w2 g, D2 = sum w0 w1 d2 g
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
             D1r += w0 * ur;  D1i += w0 * ui;
             D2r += w0 * tr;  D2i += w0 * ti;
         }
-        if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, stage);
+        if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, lidx, stage);
         __syncthreads();
     }
     if (it.active) {
@@ -149,8 +149,8 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     }
     const int zlo = zc - m + 1 - it.zbeg;
     constexpr int NF = ps_nf<W>();
-    int off[NF];
-    ps_offsets<NF>(a, it, m, off);
+    int off[NF], lidx[NF];
+    ps_offsets<NF>(a, it, m, off, lidx);
     c_t<T> *grid = (c_t<T> *)a.grid_out;
     const int64_t plane = (int64_t)a.n1 * a.n2;
     __syncthreads();
@@ -208,10 +208,11 @@ int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes) {
 // ------------------------------------------------------------ dispatch ----
 template <typename T, int W, int PPT>
 static int interp_ppt(nfft3_plan_impl *p, const void *grid, void *f) {
-    PSArgs a = ps_args(p);
+    PSArgs a = interp_args(p);
+    if (!interp_layout_ok(p, a)) return NFFT3_ERR_INVALID_ARG;
     a.grid = grid;
     a.out = f;
-    const size_t lds = ps_lds(p, 2);
+    const size_t lds = interp_lds(p, a);
     allow_lds((const void *)interp_ps_kernel<T, W, PPT>, lds);
     hipLaunchKernelGGL((interp_ps_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
                        p->stream, a);

@@ -2,6 +2,8 @@
 // points), shared by the stand-alone kernels and the persistent batched
 // kernel.  See interp.hip for the scheme.
 #pragma once
+#include <numeric>
+
 #include "internal.h"
 
 namespace nfft3 {
@@ -91,7 +93,8 @@ struct PSArgs {
     int deg;
     int n0, n1, n2;
     int By, Bx, ntx;
-    int pad8;               // pad the plane row stride to 8 mod 16 elements
+    int pxp;                // interp: LDS row stride of a staged plane (elements); 0 = unpadded
+    int qinv;               // interp: inverse of (row stride in 16-B units / D) mod 16/D
 };
 
 // Per-workgroup setup shared by the three kernels.
@@ -130,7 +133,7 @@ __device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int
     it.PY = a.By + 2 * m - 1;
     it.PX = a.Bx + 2 * m - 1;
     it.psz = it.PY * it.PX;
-    it.PXp = a.pad8 ? it.PX + ((8 - it.PX % 16) + 16) % 16 : it.PX;
+    it.PXp = a.pxp ? a.pxp : it.PX;
     return it;
 }
 
@@ -140,9 +143,10 @@ __device__ __forceinline__ PSItem ps_item(const PSArgs &a, int m, int4 &item) {
 }
 
 // Offsets (within a plane) of the elements this thread stages; slots past
-// the region point at element 0 so that every slot can be loaded.
+// the region point at element 0 so that every slot can be loaded.  lidx is
+// the element's LDS index in a plane of row stride it.PXp.
 template <int NF>
-__device__ __forceinline__ void ps_offsets(const PSArgs &a, const PSItem &it, int m, int *off) {
+__device__ __forceinline__ void ps_offsets(const PSArgs &a, const PSItem &it, int m, int *off, int *lidx) {
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         const int e = threadIdx.x + k * kPsThreads;
@@ -151,8 +155,10 @@ __device__ __forceinline__ void ps_offsets(const PSArgs &a, const PSItem &it, in
             const int gy = wrapi(it.y0 - m + 1 + ly, a.n1);
             const int gx = wrapi(it.x0 - m + 1 + lx, a.n2);
             off[k] = gy * a.n2 + gx;
+            lidx[k] = ly * it.PXp + lx;
         } else {
             off[k] = 0;
+            lidx[k] = 0;
         }
     }
 }
@@ -169,134 +175,262 @@ __device__ __forceinline__ void ps_fetch(const c_t<T> *__restrict__ grid, const 
     for (int k = 0; k < NF; ++k) v[k] = g[off[k]];
 }
 
+// Direct staging for unpadded complex<double> planes: each 16-byte element
+// goes from global memory straight into LDS (global_load_lds_dwordx4; lane l
+// of a wavefront writes the l-th 16 bytes after the wavefront's LDS base),
+// so no registers hold the next plane.  Completion is tracked by vmcnt: wait
+// for it before the barrier that publishes the plane.
+template <int NF>
+__device__ __forceinline__ void ps_fetch_lds(const c_t<double> *__restrict__ grid, const PSItem &it, const int *off,
+                                             int64_t zoff, c_t<double> *buf) {
+    const c_t<double> *g = grid + zoff;
+    const int wbase = threadIdx.x & ~63;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        const int e = threadIdx.x + k * kPsThreads;
+        if (e < it.psz)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(g + off[k]),
+                (__attribute__((address_space(3))) void *)(buf + k * kPsThreads + wbase), 16, 0, 0);
+    }
+}
+
 template <typename T, int NF>
-__device__ __forceinline__ void ps_store(c_t<T> *buf, const PSItem &it, const vec2_t<T> *v) {
+__device__ __forceinline__ void ps_store(c_t<T> *buf, const PSItem &it, const int *lidx, const vec2_t<T> *v) {
     vec2_t<T> *b = reinterpret_cast<vec2_t<T> *>(buf);
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         const int e = threadIdx.x + k * kPsThreads;
-        if (e < it.psz) b[e] = v[k];
+        if (e < it.psz) b[lidx[k]] = v[k];
     }
-}
-
-// LDS bank spreading.  Lane l of a wavefront natively takes sorted point
-// base + 64 w + l (z-adjacent points, so the wave is active on the same
-// planes).  The stencil read of an instruction is, per lane, plane element
-// (row + yo) * PX + (col + xo): the bank a lane hits is fixed by its class
-// c = (yo * PX + xo) mod 16.  Sorting the wave's 64 points by class and
-// dealing them out transposed (sorted position p -> lane 16 (p mod 4) + p/4)
-// gives each 16-lane (and 8-lane) issue group distinct classes when the
-// classes are balanced, instead of random ones.  Returns the lane-local index
-// (0..255) of the point this thread takes.
-__device__ __forceinline__ int wave_spread(const PSArgs &a, const PSItem &it, int base, int end) {
-    const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
-    const int pk = base + threadIdx.x;
-    const bool valid = pk < end;
-    int c = 16;                     // invalid lanes sort last
-    if (valid) {
-        float f;
-        const int yc = cell_frac<float>(a.xs[3 * pk + 1], a.n1, f);
-        const int xc = cell_frac<float>(a.xs[3 * pk + 2], a.n2, f);
-        c = ((yc - it.y0) * it.PX + (xc - it.x0)) & 15;
-    }
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int pos = 0, rank = 0;
-#pragma unroll
-    for (int q = 0; q <= 16; ++q) {
-        const uint64_t mq = __ballot(c == q);
-        if (q < c) pos += __popcll(mq);
-        if (q == c) rank = __popcll(mq & below);
-    }
-    pos += rank;                    // position in class-sorted order, 0..63
-    const int tgt = 16 * (pos & 3) + (pos >> 2);
-    const int src = __builtin_amdgcn_ds_permute(tgt << 2, lane);
-    return wbase + src;
 }
 
 // ------------------------------------------------------------ interp ----
+// Stencil reads without LDS bank conflicts.
+//
+// gfx950 serves a 16-byte-per-lane LDS read 16 lanes per clock; two lanes of
+// one 16-lane group conflict when their addresses share a 16-byte bank group
+// (address/16 mod 16).  The stencil is read in 16-byte units: one
+// complex<double>, or an aligned pair of complex<float> (a row of W values is
+// read as W/2+1 pairs, the column weights shifted to the stencil's first
+// element and zero outside it).  At row step j a lane reads stencil row
+// (j + t) mod W; the plane row stride RU (in units) is chosen with
+// W*RU = 0 mod 16, so the bank group of its k-th unit at step j is
+// u + RU*t + RU*j + k mod 16, u being the stencil's first unit.  RU*t runs over
+// the multiples of D = 16/gcd(W, 16) (= gcd(RU, 16)), so each lane picks the
+// rotation t that puts it on a target group of its own within its coset
+// u mod D; with D = 1 (complex<double>, m = 8) every 16-lane group reads
+// conflict-free.  For the complex<float> pairs with D = 2, a stencil starting
+// on an even element can also be read from one unit earlier (weights shifted
+// by two), which flips its coset: those lanes balance the two cosets of each
+// group.  The y weights are rotated with the rows, once per point.
+
+template <typename T> struct LdsUnit;
+template <> struct LdsUnit<double> {
+    using type = vec2_t<double>;
+    static constexpr int EPU = 1;     // elements per 16-byte unit
+};
+template <> struct LdsUnit<float> {
+    using type = float __attribute__((ext_vector_type(4)));
+    static constexpr int EPU = 2;
+};
+
+constexpr int cgcd(int a, int b) { return b ? cgcd(b, a % b) : a; }
+
+// w[j] <- w[(j + t) mod W] for 0 <= t < NT (NT a power of two <= W).  The
+// selects are done on the bit patterns: a select between two elements of the
+// same array would otherwise be folded into one load at a lane-dependent
+// index, which moves the array out of registers.
+__device__ __forceinline__ float bitsel(bool c, float a, float b) {
+    const unsigned m = c ? ~0u : 0u;
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+__device__ __forceinline__ double bitsel(bool c, double a, double b) {
+    const unsigned long long m = c ? ~0ull : 0ull;
+    return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(a) & m) |
+                                            ((unsigned long long)__double_as_longlong(b) & ~m)));
+}
+
+template <typename T, int W, int NT>
+__device__ __forceinline__ void rotate_rows(T *w, int t) {
+#pragma unroll
+    for (int b = 1; b < NT; b <<= 1) {
+        const bool on = (t & b) != 0;
+        T tmp[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) tmp[j] = bitsel(on, w[(j + b) % W], w[j]);
+#pragma unroll
+        for (int j = 0; j < W; ++j) w[j] = tmp[j];
+    }
+}
+
 // Point slot k of thread t is sorted index item.y + k*256 + t: each slot's
 // wavefronts hold z-adjacent points, so they are active on the same planes.
 template <typename T, int W, int PPT>
 __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, unsigned char *smem_raw) {
     constexpr int m = W / 2;
+    using U = typename LdsUnit<T>::type;
+    constexpr int EPU = LdsUnit<T>::EPU;
+    constexpr int NR = EPU == 1 ? W : W / 2 + 1;   // units read per stencil row
+    constexpr int NW = NR * EPU;                   // column weights per row
+    constexpr int D = 16 / cgcd(W, 16);            // cosets of bank groups
+    constexpr int NT = 16 / D;                     // distinct rotations
     const int4 item = a.items[item_index];
     const PSItem it = ps_range(a, m, item.x, item.y, item.z);
+    const int RU = it.PXp / EPU;
+    const int bufsz = it.PY * it.PXp;
     c_t<T> *buf0 = reinterpret_cast<c_t<T> *>(smem_raw);
-    c_t<T> *buf1 = buf0 + it.psz;
-    T *scoef = reinterpret_cast<T *>(buf1 + it.psz);
+    c_t<T> *buf1 = buf0 + bufsz;
+    T *scoef = reinterpret_cast<T *>(buf1 + bufsz);
     const T *coef = (const T *)a.coef;
     const int nc = W * (a.deg + 1);
     for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
+    // the pad columns are read (with zero weight) by the pair layout: clear
+    // them once; staging never writes them
+    const int npad = it.PXp - it.PX;
+    for (int e = threadIdx.x; e < 2 * it.PY * npad; e += kPsThreads) {
+        const int r = e / npad, col = it.PX + (e - r * npad);
+        buf0[r * it.PXp + col] = cmk<T>(0, 0);     // rows 0 .. 2 PY - 1 span both buffers
+    }
 
-    T w1[PPT][W], w2[PPT][W];
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint64_t gmask = 0xFFFFull << (16 * (lane >> 4));
+    T w1[PPT][W], wt[PPT][NW];
     T f0[PPT], ar[PPT], ai[PPT];
-    int zlo[PPT], pofs[PPT], pidx[PPT];
+    int zlo[PPT], ub0[PPT], ub1[PPT], tt[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int pk = item.y + k * kPsThreads + wave_spread(a, it, item.y + k * kPsThreads, item.z);
-        pidx[k] = pk;
+        const int pk = item.y + k * kPsThreads + threadIdx.x;
+        const bool active = pk < item.z;
         ar[k] = 0;
         ai[k] = 0;
         zlo[k] = -4 * W;     // never active
-        pofs[k] = -1;
         f0[k] = 0;
-        if (pk < item.z) {
+        int s = 0;           // stencil's first element in the plane
+        T w2[W];
+#pragma unroll
+        for (int r = 0; r < W; ++r) { w1[k][r] = 0; w2[r] = 0; }
+        if (active) {
             const double *xp = a.xs + 3 * pk;
             T f1, f2;
             const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
             const int yc = cell_frac<T>(xp[1], a.n1, f1);
             const int xc = cell_frac<T>(xp[2], a.n2, f2);
-            pofs[k] = (yc - it.y0) * it.PX + (xc - it.x0);
+            s = (yc - it.y0) * it.PXp + (xc - it.x0);
             zlo[k] = zc - m + 1 - it.zbeg;      // first plane index of the stencil
             window_weights<T, W>(f1, coef, a.deg, w1[k]);
-            window_weights<T, W>(f2, coef, a.deg, w2[k]);
+            window_weights<T, W>(f2, coef, a.deg, w2);
         }
+        int u = s / EPU;
+        if constexpr (EPU == 2 && D == 2) {
+            // even starts (s >= 2, so the earlier unit exists) may take either coset
+            const bool flex = active && !(s & 1) && s >= 2;
+            const uint64_t fixed0 = __ballot(active && !flex && !(u & 1));
+            const uint64_t flexm = __ballot(flex);
+            const int need0 = 8 - __popcll(fixed0 & gmask);
+            if (flex) {
+                const bool want0 = __popcll(flexm & gmask & below) < need0;
+                if (((u & 1) == 0) != want0) u -= 1;
+            }
+        }
+        const int sh = s - u * EPU;            // stencil offset in the read window: 0, 1 or 2
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            T v = (c < W) ? w2[c] : (T)0;
+            if (EPU == 2) {
+                const T v1 = (c >= 1 && c - 1 < W) ? w2[c - 1] : (T)0;
+                const T v2 = (c >= 2 && c - 2 < W) ? w2[c - 2] : (T)0;
+                v = sh == 0 ? v : (sh == 1 ? v1 : v2);
+            }
+            wt[k][c] = v;
+        }
+        // rank within the lane's coset and 16-lane group -> target bank group
+        const int cs = u & (D - 1);
+        int rank = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const uint64_t mc = __ballot(active && cs == c);
+            if (cs == c) rank = __popcll(mc & gmask & below);
+        }
+        const int target = cs + D * (rank & (NT - 1));
+        const int delta = (target - u) & 15;   // a multiple of D
+        const int t = ((delta / D) * a.qinv) & (NT - 1);
+        rotate_rows<T, W, NT>(w1[k], t);
+        tt[k] = t;
+        ub0[k] = u + t * RU;
+        ub1[k] = ub0[k] - W * RU;
     }
 
     constexpr int NF = ps_nf<W>();
-    int off[NF];
-    ps_offsets<NF>(a, it, m, off);
+    int off[NF], lidx[NF];
+    ps_offsets<NF>(a, it, m, off, lidx);
     const c_t<T> *grid = (const c_t<T> *)a.grid;
     const int64_t plane = (int64_t)a.n1 * a.n2;
-    vec2_t<T> stage[NF];
-    ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
-    ps_store<T, NF>(buf0, it, stage);
+    // complex<double> planes with an odd row length need no padding: stage
+    // them directly (the host sets the row stride to PX in that case)
+    constexpr bool kDirect = EPU == 1 && W == 16;
+    vec2_t<T> stage[kDirect ? 1 : NF];
+    if constexpr (kDirect) {
+        ps_fetch_lds<NF>((const c_t<double> *)grid, it, off, (int64_t)wrapi(it.zbeg, a.n0) * plane,
+                         (c_t<double> *)buf0);
+        __builtin_amdgcn_s_waitcnt(0);
+    } else {
+        ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
+        ps_store<T, NF>(buf0, it, lidx, stage);
+    }
     __syncthreads();
 
     for (int i = 0; i < it.nplanes; ++i) {
         const bool more = i + 1 < it.nplanes;
-        if (more) ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, stage);
-        const c_t<T> *pl = (i & 1) ? buf1 : buf0;
+        if (more) {
+            const int64_t zoff = (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane;
+            if constexpr (kDirect)
+                ps_fetch_lds<NF>((const c_t<double> *)grid, it, off, zoff, (c_t<double> *)((i & 1) ? buf0 : buf1));
+            else
+                ps_fetch<T, NF>(grid, off, zoff, stage);
+        }
+        const U *pl = reinterpret_cast<const U *>((i & 1) ? buf1 : buf0);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int r0 = i - zlo[k];
             if (r0 >= 0 && r0 < W) {
                 const T w0 = piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
                 T sr = 0, si = 0;
-                const c_t<T> *base = pl + pofs[k];
 #pragma unroll
-                for (int r1 = 0; r1 < W; ++r1) {
-                    const c_t<T> *row = base + r1 * it.PX;
+                for (int j = 0; j < W; ++j) {
+                    const U *row = pl + ((j + tt[k] < W) ? ub0[k] : ub1[k]) + j * RU;
                     T cr = 0, ci = 0;
 #pragma unroll
-                    for (int r2 = 0; r2 < W; ++r2) {
-                        const c_t<T> g = row[r2];
-                        cr += w2[k][r2] * g.x;
-                        ci += w2[k][r2] * g.y;
+                    for (int c = 0; c < NR; ++c) {
+                        const U g = row[c];
+                        if constexpr (EPU == 1) {
+                            cr += wt[k][c] * g.x;
+                            ci += wt[k][c] * g.y;
+                        } else {
+                            cr += wt[k][2 * c] * g.x;
+                            ci += wt[k][2 * c] * g.y;
+                            cr += wt[k][2 * c + 1] * g.z;
+                            ci += wt[k][2 * c + 1] * g.w;
+                        }
                     }
-                    sr += w1[k][r1] * cr;
-                    si += w1[k][r1] * ci;
+                    sr += w1[k][j] * cr;
+                    si += w1[k][j] * ci;
                 }
                 ar[k] += w0 * sr;
                 ai[k] += w0 * si;
             }
         }
-        if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, stage);
+        if constexpr (kDirect) {
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+            if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, lidx, stage);
+        }
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int pk = pidx[k];
+        const int pk = item.y + k * kPsThreads + threadIdx.x;
         if (pk < item.z) ((c_t<T> *)a.out)[a.perm[pk]] = cmk<T>(ar[k], ai[k]);
     }
 }
@@ -319,8 +453,52 @@ inline PSArgs ps_args(const nfft3_plan_impl *p) {
     a.By = p->bins.By;
     a.Bx = p->bins.Bx;
     a.ntx = p->bins.ntx;
-    a.pad8 = 0;
+    a.pxp = 0;
+    a.qinv = 0;
     return a;
+}
+
+// Row stride of the interp kernel's staged planes: at least PX (+2 elements
+// read past the stencil by the complex<float> pair layout), a whole number RU
+// of 16-byte units with gcd(RU mod 16, 16) = D = 16/gcd(W, 16); and the
+// inverse of RU/D modulo 16/D.
+inline void interp_layout(const nfft3_plan_impl *p, PSArgs &a) {
+    const int W = 2 * p->m;
+    const int epu = p->elt == 16 ? 1 : 2;
+    const int PX = p->bins.Bx + W - 1;
+    const int D = 16 / std::gcd(W, 16);
+    int pxp = PX + (epu == 2 ? 2 : 0);
+    for (;; ++pxp) {
+        if (pxp % epu) continue;
+        const int q = (pxp / epu) % 16;
+        if (q != 0 && std::gcd(q, 16) == D) break;
+    }
+    const int NT = 16 / D;
+    const int qd = ((pxp / epu) % 16) / D;
+    int qinv = 0;
+    for (int v = 0; v < NT; ++v)
+        if ((qd * v) % NT == 1 % NT) { qinv = v; break; }
+    a.pxp = pxp;
+    a.qinv = qinv;
+}
+
+inline PSArgs interp_args(const nfft3_plan_impl *p) {
+    PSArgs a = ps_args(p);
+    interp_layout(p, a);
+    return a;
+}
+
+// The direct (global -> LDS) staging of complex<double>, m = 8 writes each
+// wavefront's elements contiguously, so it needs unpadded rows.
+inline bool interp_layout_ok(const nfft3_plan_impl *p, const PSArgs &a) {
+    return !(p->elt == 16 && p->m == 8) || a.pxp == p->bins.Bx + 2 * p->m - 1;
+}
+
+// LDS bytes of the interp kernel: two staged planes + the coefficients.
+inline size_t interp_lds(const nfft3_plan_impl *p, const PSArgs &a) {
+    const int W = 2 * p->m;
+    const size_t bufsz = (size_t)(p->bins.By + W - 1) * a.pxp;
+    return 2 * bufsz * p->elt + (size_t)W * (p->deg + 1) * (p->elt / 2);
 }
 
 // LDS bytes of the window-sum kernels: nbuf staged planes + the coefficients.
