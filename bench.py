@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--M", type=int, default=10_000_000)
     ap.add_argument("--m32", type=int, default=4)
     ap.add_argument("--m64", type=int, default=8)
-    ap.add_argument("--cpu-sample", type=int, default=384,
+    ap.add_argument("--cpu-sample", type=int, default=10_000,
                     help="points of the seeded sample evaluated by the oracle (CPU baseline + error)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
     ap.add_argument("--forms", default="fp32,fp64")
@@ -126,7 +126,7 @@ def main():
         ms_interp = ia.elapsed_time(ib) / args.steps
         f = out[torch.from_numpy(sample).to(dev)].cpu().numpy() if len(sample) else None
         results[form] = dict(m=m, dtype=dt, ms_step=ms_step, wall_s=wall, t_set=t_set, ms_grid=ms_grid,
-                             ms_interp=ms_interp, f_sample=f, n=plan.n)
+                             ms_interp=ms_interp, f_sample=f, n=plan.n, tuning=plan.tuning())
         log(f"{form} m={m}: {ms_step:.3f} ms/step ({M / ms_step * 1e3:.3e} pts/s); grid stage {ms_grid:.3f} ms, "
             f"interp stage {ms_interp:.3f} ms; set_points {t_set * 1e3:.1f} ms")
         plan.close()
@@ -191,6 +191,7 @@ def main():
             "m": rr["m"], "points_per_s": M / (rr["ms_step"] * 1e-3), "ms_per_step": rr["ms_step"],
             "ms_grid_stage": rr["ms_grid"], "ms_interp_stage": rr["ms_interp"],
             "set_points_ms": rr["t_set"] * 1e3, "wall_s_timed": rr["wall_s"],
+            "tile": rr["tuning"][0], "points_per_item": rr["tuning"][1],
             "rel_l2": errs.get(form, (None, None))[0], "rel_linf": errs.get(form, (None, None))[1],
         }
     print(json.dumps(line), flush=True)

@@ -138,6 +138,27 @@ int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int 
 int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
                       void *const *out_dev, int deriv_mask);
 
+/* ---- Tuning of the point binning (not in the paper; the window sums of
+ * Sec. 2.2.1 at the plan's points are computed the same way for every
+ * setting, only faster or slower) ---------------------------------------- */
+
+/* tile: edge, in grid cells, of the (y, x) tiles the points are binned into
+ * (8, 16 or 32; the plane a work group stages in LDS is the tile plus the
+ * 2m-1 halo).  items: points per work item of the window-sum kernels (256
+ * or 512).  0 keeps the current value.  Defaults: tile 32, items 512.  A changed setting drops the plan's
+ * points: call nfft3_set_points again.  INVALID_ARG for other values. */
+int nfft3_set_tuning(nfft3_plan_t p, int tile, int items);
+int nfft3_get_tuning(nfft3_plan_t p, int *tile, int *items);
+
+/* Autotuner: times nfft3_trafo for every (tile, items) candidate on the
+ * caller's points and coefficients (each candidate re-runs
+ * nfft3_set_points on x_dev), keeps the fastest and leaves the points set
+ * with it.  f_dev (M values) receives the transform outputs; reps >= 1
+ * timed transforms per candidate (median).  Synchronizes the plan's
+ * stream.  *tile_out / *items_out (may be NULL) receive the choice. */
+int nfft3_autotune(nfft3_plan_t p, int64_t M, const double *x_dev, const void *fhat_dev, void *f_dev,
+                   int reps, int *tile_out, int *items_out);
+
 /* Release every buffer of the plan.  NULL is a no-op. */
 int nfft3_destroy(nfft3_plan_t p);
 

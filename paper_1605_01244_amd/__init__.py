@@ -141,6 +141,38 @@ class Plan:
         check(lib.nfft3_grad_points(self._h, _ptr(fhat), _ptr(G), _ptr(out)), "nfft3_grad_points")
         return out
 
+    # -- binning tuning ------------------------------------------------------
+    def set_tuning(self, tile: int = 0, items: int = 0) -> None:
+        """Tile edge (8/16/32 cells) and points per work item (256/512) of the
+        window sums; 0 keeps a value.  A change drops the points."""
+        check(lib.nfft3_set_tuning(self._h, int(tile), int(items)), "nfft3_set_tuning")
+        M = ctypes.c_int64()
+        check(lib.nfft3_get_info(self._h, None, ctypes.byref(M)), "nfft3_get_info")
+        if int(M.value) != self.M:      # the points were dropped
+            self.M = int(M.value)
+            self.epoch += 1
+
+    def tuning(self):
+        t, i = ctypes.c_int(), ctypes.c_int()
+        check(lib.nfft3_get_tuning(self._h, ctypes.byref(t), ctypes.byref(i)), "nfft3_get_tuning")
+        return int(t.value), int(i.value)
+
+    def autotune(self, x: torch.Tensor, fhat: torch.Tensor, reps: int = 3):
+        """Time trafo for every binning candidate on these points and
+        coefficients, keep the fastest (points stay set).  Returns (tile, items)."""
+        if x.dim() != 2 or x.shape[1] != 3 or x.dtype != torch.float64 or x.device != self.device:
+            raise TypeError("points must be (M, 3) float64 on the plan's device")
+        x = x.contiguous()
+        fhat = self._coeffs(fhat)
+        out = torch.empty(x.shape[0], dtype=self.dtype, device=self.device)
+        t, i = ctypes.c_int(), ctypes.c_int()
+        self._bind_stream()
+        check(lib.nfft3_autotune(self._h, x.shape[0], _ptr(x), _ptr(fhat), _ptr(out), int(reps),
+                                 ctypes.byref(t), ctypes.byref(i)), "nfft3_autotune")
+        self.M = int(x.shape[0])
+        self.epoch += 1
+        return int(t.value), int(i.value)
+
     # -- stage access (tests, benchmarks) ------------------------------------
     def stage_grid(self, fhat: torch.Tensor, deriv_axis: int = -1) -> None:
         fhat = self._coeffs(fhat)

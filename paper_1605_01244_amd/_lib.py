@@ -55,6 +55,9 @@ def _load() -> ctypes.CDLL:
         "nfft3_grad_points": ([vp, vp, vp, vp], ci),
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),
         "nfft3_batch_trafo": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
+        "nfft3_set_tuning": ([vp, ci, ci], ci),
+        "nfft3_get_tuning": ([vp, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
+        "nfft3_autotune": ([vp, i64, vp, vp, vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
         "nfft3_destroy": ([vp], ci),
         "nfft3_strerror": ([ci], ctypes.c_char_p),
         "nfft3_last_hip_error": ([], ctypes.c_char_p),

@@ -156,6 +156,13 @@ static void free_points(nfft3_plan_impl *p) {
     p->cap_pts = 0;
 }
 
+static void free_bins(nfft3_plan_impl *p) {
+    hipFree(p->bins.counts); p->bins.counts = nullptr;
+    hipFree(p->bins.offsets); p->bins.offsets = nullptr;
+    hipFree(p->bins.scratch); p->bins.scratch = nullptr;
+    hipFree(p->bins.tile_items); p->bins.tile_items = nullptr;
+    hipFree(p->bins.tile_item_off); p->bins.tile_item_off = nullptr;
+}
 static void free_plan(nfft3_plan_impl *p) {
     if (!p) return;
     hipFree(p->grid);
@@ -164,11 +171,7 @@ static void free_plan(nfft3_plan_impl *p) {
     hipFree(p->wcoef);
     free_points(p);
     hipFree(p->flag);
-    hipFree(p->bins.counts);
-    hipFree(p->bins.offsets);
-    hipFree(p->bins.scratch);
-    hipFree(p->bins.tile_items);
-    hipFree(p->bins.tile_item_off);
+    free_bins(p);
     hipFree(p->sub.items);
 }
 
@@ -222,6 +225,27 @@ static int upload_twiddles(int n, void **dst) {
     return NFFT3_OK;
 }
 
+// Point tiles of edge T (a power of two <= kMaxTile whose plane, tile +
+// stencil halo, fits the window-sum kernels' staging of kMaxPlane elements)
+// and the binning buffers sized for them.
+static int alloc_bins(nfft3_plan_impl *p, int T) {
+    while (T > 1 && (T + 2 * p->m - 1) * (T + 2 * p->m - 1) > kMaxPlane) T /= 2;
+    free_bins(p);
+    p->bins.By = (int)std::min<int64_t>(T, p->n[1]);
+    p->bins.Bx = (int)std::min<int64_t>(T, p->n[2]);
+    p->bins.nty = (int)((p->n[1] + p->bins.By - 1) / p->bins.By);
+    p->bins.ntx = (int)((p->n[2] + p->bins.Bx - 1) / p->bins.Bx);
+    const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
+    const int64_t nb = ntiles * p->n[0];
+    p->bins.nbins = nb;
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nb));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nb + 1)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nb / 1024 + 2)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * ntiles));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (ntiles + 1)));
+    return NFFT3_OK;
+}
+
 static int build_plan(nfft3_plan_impl *p) {
     const bool f64 = p->dtype == NFFT3_C128;
     NFFT3_HIP_TRY(hipGetDevice(&p->device));
@@ -250,27 +274,15 @@ static int build_plan(nfft3_plan_impl *p) {
     p->deg = deg;
     int rc = f64 ? upload_real<double>(coef, &p->wcoef) : upload_real<float>(coef, &p->wcoef);
     if (rc) return rc;
-    // point tiles: the largest power of two <= kMaxTile whose plane (tile +
-    // stencil halo) fits the window-sum kernels' staging (kMaxPlane elements)
-    int T = kMaxTile;
-    while (T > 1 && (T + 2 * p->m - 1) * (T + 2 * p->m - 1) > kMaxPlane) T /= 2;
-    p->bins.By = (int)std::min<int64_t>(T, p->n[1]);
-    p->bins.Bx = (int)std::min<int64_t>(T, p->n[2]);
-    p->bins.nty = (int)((p->n[1] + p->bins.By - 1) / p->bins.By);
-    p->bins.ntx = (int)((p->n[2] + p->bins.Bx - 1) / p->bins.Bx);
-    // points per thread of the interpolation kernel (registers hold the y/x
-    // weights of every point a thread owns)
-    p->sub.maxpts = kItemPts * (f64 ? 2 : 1);
-    const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
-    const int64_t nb = ntiles * p->n[0];
-    p->bins.nbins = nb;
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nb));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nb + 1)));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nb / 1024 + 2)));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * ntiles));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (ntiles + 1)));
-    return NFFT3_OK;
+    // points per work item of the window sums (a thread holds the y/x
+    // weights of every point it owns); 512 measured fastest for both forms
+    // at N = 256^3, M = 1e7
+    p->sub.maxpts = 2 * kItemPts;
+    p->tile_req = kMaxTile;
+    return alloc_bins(p, kMaxTile);
 }
+
+
 
 }  // namespace nfft3
 
@@ -425,6 +437,84 @@ const char *nfft3_strerror(int code) {
 }
 
 const char *nfft3_last_hip_error(void) { return g_last_hip.c_str(); }
+
+int nfft3_set_tuning(nfft3_plan_t p, int tile, int items) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (tile != 0 && tile != 8 && tile != 16 && tile != 32) return NFFT3_ERR_INVALID_ARG;
+    if (items != 0 && items != kItemPts && items != 2 * kItemPts) return NFFT3_ERR_INVALID_ARG;
+    int cur_tile = 0, cur_items = 0;
+    nfft3_get_tuning(p, &cur_tile, &cur_items);
+    if (tile == 0) tile = cur_tile;
+    if (items == 0) items = cur_items;
+    if (tile == cur_tile && items == cur_items) return NFFT3_OK;
+    NFFT3_HIP_TRY(hipStreamSynchronize(p->stream));
+    p->have_points = false;
+    p->M = 0;
+    p->sub.maxpts = items;
+    if (tile != cur_tile) {
+        p->tile_req = tile;
+        return alloc_bins(p, tile);
+    }
+    return NFFT3_OK;
+}
+
+int nfft3_get_tuning(nfft3_plan_t p, int *tile, int *items) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (tile) *tile = p->tile_req;
+    if (items) *items = p->sub.maxpts;
+    return NFFT3_OK;
+}
+
+int nfft3_autotune(nfft3_plan_t p, int64_t M, const double *x, const void *fhat, void *f, int reps, int *tile_out,
+                   int *items_out) {
+    if (!p) return NFFT3_ERR_NULL;
+    if (!fhat || (M > 0 && (!x || !f))) return NFFT3_ERR_NULL;
+    if (reps < 1) return NFFT3_ERR_INVALID_ARG;
+    const int tiles[] = {16, 32};
+    const int items[] = {kItemPts, 2 * kItemPts};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    NFFT3_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return NFFT3_ERR_HIP;
+    }
+    int best_t = 0, best_i = 0, rc = NFFT3_OK;
+    float best = 0.f;
+    for (int t : tiles) {
+        for (int it : items) {
+            rc = nfft3_set_tuning(p, t, it);
+            if (!rc) rc = nfft3_set_points(p, M, x);
+            if (!rc) rc = nfft3_trafo(p, fhat, f);     // warm-up
+            std::vector<float> ms;
+            for (int r = 0; r < reps && !rc; ++r) {
+                if (hipEventRecord(e0, p->stream) != hipSuccess) { rc = NFFT3_ERR_HIP; break; }
+                rc = nfft3_trafo(p, fhat, f);
+                if (rc) break;
+                if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = NFFT3_ERR_HIP;
+                    break;
+                }
+                float v = 0.f;
+                hipEventElapsedTime(&v, e0, e1);
+                ms.push_back(v);
+            }
+            if (rc) break;
+            std::sort(ms.begin(), ms.end());
+            const float med = ms[ms.size() / 2];
+            if (best_t == 0 || med < best) { best = med; best_t = t; best_i = it; }
+        }
+        if (rc) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = nfft3_set_tuning(p, best_t, best_i);
+    if (!rc) rc = nfft3_set_points(p, M, x);
+    if (rc) return rc;
+    if (tile_out) *tile_out = best_t;
+    if (items_out) *items_out = best_i;
+    return NFFT3_OK;
+}
 
 int nfft3_get_info(nfft3_plan_t p, int64_t n_out[3], int64_t *M_out) {
     if (!p) return NFFT3_ERR_NULL;

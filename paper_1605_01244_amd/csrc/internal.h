@@ -115,6 +115,7 @@ struct nfft3_plan_impl {
     int *rank = nullptr;      // per caller index: rank inside bin (scratch)
     int *flag = nullptr;      // device status word (non-finite points)
     Bins bins;
+    int tile_req = kMaxTile;  // requested tile edge (By, Bx may be smaller)
     Subproblems sub;
     int64_t epoch = 0;        // bumps at every set_points
 };

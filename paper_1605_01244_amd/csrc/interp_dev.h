@@ -176,22 +176,25 @@ __device__ __forceinline__ void ps_fetch(const c_t<T> *__restrict__ grid, const 
 }
 
 // Direct staging for unpadded complex<double> planes: each 16-byte element
-// goes from global memory straight into LDS (global_load_lds_dwordx4; lane l
-// of a wavefront writes the l-th 16 bytes after the wavefront's LDS base),
-// so no registers hold the next plane.  Completion is tracked by vmcnt: wait
-// for it before the barrier that publishes the plane.
+// goes from global memory straight into LDS (buffer_load_dwordx4 ... lds;
+// lane l of a wavefront writes the l-th 16 bytes after the wavefront's LDS
+// base), so no registers hold the next plane.  The buffer resource spans one
+// plane (offsets past it would read zero).  Completion is tracked by vmcnt:
+// wait for it before the barrier that publishes the plane.  (The buffer form
+// keeps the LDS counter free for selective waits on the stencil reads.)
 template <int NF>
-__device__ __forceinline__ void ps_fetch_lds(const c_t<double> *__restrict__ grid, const PSItem &it, const int *off,
-                                             int64_t zoff, c_t<double> *buf) {
-    const c_t<double> *g = grid + zoff;
+__device__ __forceinline__ void ps_fetch_lds(const c_t<double> *__restrict__ plane, int plane_bytes,
+                                             const PSItem &it, const int *off, c_t<double> *buf) {
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)plane, (short)0, plane_bytes, 0x00020000);
     const int wbase = threadIdx.x & ~63;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
         const int e = threadIdx.x + k * kPsThreads;
         if (e < it.psz)
-            __builtin_amdgcn_global_load_lds(
-                (const void *)(g + off[k]),
-                (__attribute__((address_space(3))) void *)(buf + k * kPsThreads + wbase), 16, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rsrc, (__attribute__((address_space(3))) void *)(buf + k * kPsThreads + wbase), 16, off[k] * 16, 0,
+                0, 0);
     }
 }
 
@@ -236,6 +239,22 @@ template <> struct LdsUnit<float> {
 };
 
 constexpr int cgcd(int a, int b) { return b ? cgcd(b, a % b) : a; }
+
+// largest divisor of n that is at most 7 (a chunk of stencil-row reads)
+constexpr int row_chunk(int n) {
+    for (int c = 7; c > 1; --c)
+        if (n % c == 0) return c;
+    return 1;
+}
+
+// Chunks of stencil-row reads issued ahead of the one being consumed.  The
+// complex<double> form (16 reads of 16 B per row, two waves per SIMD) needs
+// them in flight; the complex<float> form (5 reads per row, more waves)
+// runs fastest with the compiler's own schedule (measured on MI355X).
+template <typename T>
+constexpr int interp_lookahead(int ch) {
+    return sizeof(T) == 4 ? 0 : (15 / ch - 1 < 2 ? 15 / ch - 1 : 2);
+}
 
 // w[j] <- w[(j + t) mod W] for 0 <= t < NT (NT a power of two <= W).  The
 // selects are done on the bit patterns: a select between two elements of the
@@ -371,8 +390,9 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
     // them directly (the host sets the row stride to PX in that case)
     constexpr bool kDirect = EPU == 1 && W == 16;
     vec2_t<T> stage[kDirect ? 1 : NF];
+    const int plane_bytes = (int)(plane * (int64_t)sizeof(c_t<T>));
     if constexpr (kDirect) {
-        ps_fetch_lds<NF>((const c_t<double> *)grid, it, off, (int64_t)wrapi(it.zbeg, a.n0) * plane,
+        ps_fetch_lds<NF>((const c_t<double> *)grid + (int64_t)wrapi(it.zbeg, a.n0) * plane, plane_bytes, it, off,
                          (c_t<double> *)buf0);
         __builtin_amdgcn_s_waitcnt(0);
     } else {
@@ -386,7 +406,8 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
         if (more) {
             const int64_t zoff = (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane;
             if constexpr (kDirect)
-                ps_fetch_lds<NF>((const c_t<double> *)grid, it, off, zoff, (c_t<double> *)((i & 1) ? buf0 : buf1));
+                ps_fetch_lds<NF>((const c_t<double> *)grid + zoff, plane_bytes, it, off,
+                                 (c_t<double> *)((i & 1) ? buf0 : buf1));
             else
                 ps_fetch<T, NF>(grid, off, zoff, stage);
         }
@@ -397,25 +418,54 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
             if (r0 >= 0 && r0 < W) {
                 const T w0 = piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
                 T sr = 0, si = 0;
+                // Reads are software-pipelined in chunks of CH units of a
+                // row: chunk q + LA is issued before chunk q is consumed, and
+                // the scheduling barriers keep that order.  At most
+                // (LA + 1) * CH <= 15 reads are outstanding, the most the LDS
+                // counter can wait on selectively.
+                constexpr int CH = row_chunk(NR);
+                constexpr int S = NR / CH;             // chunks per row
+                constexpr int LA = interp_lookahead<T>(CH);
+                constexpr int NQ = W * S;
+                U g[LA + 1][CH];
 #pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    const U *row = pl + ((j + tt[k] < W) ? ub0[k] : ub1[k]) + j * RU;
-                    T cr = 0, ci = 0;
+                for (int q = 0; q < LA; ++q) {
+                    const int j = q / S;
+                    const U *row = pl + ((j + tt[k] < W) ? ub0[k] : ub1[k]) + j * RU + (q % S) * CH;
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) {
-                        const U g = row[c];
+                    for (int c = 0; c < CH; ++c) g[q][c] = row[c];
+                }
+                T cr = 0, ci = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if (q + LA < NQ) {
+                        const int q1 = q + LA, j1 = q1 / S;
+                        const U *row = pl + ((j1 + tt[k] < W) ? ub0[k] : ub1[k]) + j1 * RU + (q1 % S) * CH;
+#pragma unroll
+                        for (int c = 0; c < CH; ++c) g[q1 % (LA + 1)][c] = row[c];
+                    }
+                    if constexpr (LA > 0) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const U v = g[q % (LA + 1)][c];
+                        const int cc = (q % S) * CH + c;
                         if constexpr (EPU == 1) {
-                            cr += wt[k][c] * g.x;
-                            ci += wt[k][c] * g.y;
+                            cr += wt[k][cc] * v.x;
+                            ci += wt[k][cc] * v.y;
                         } else {
-                            cr += wt[k][2 * c] * g.x;
-                            ci += wt[k][2 * c] * g.y;
-                            cr += wt[k][2 * c + 1] * g.z;
-                            ci += wt[k][2 * c + 1] * g.w;
+                            cr += wt[k][2 * cc] * v.x;
+                            ci += wt[k][2 * cc] * v.y;
+                            cr += wt[k][2 * cc + 1] * v.z;
+                            ci += wt[k][2 * cc + 1] * v.w;
                         }
                     }
-                    sr += w1[k][j] * cr;
-                    si += w1[k][j] * ci;
+                    if (q % S == S - 1) {
+                        sr += w1[k][q / S] * cr;
+                        si += w1[k][q / S] * ci;
+                        cr = 0;
+                        ci = 0;
+                    }
+                    if constexpr (LA > 0) __builtin_amdgcn_sched_barrier(0);
                 }
                 ar[k] += w0 * sr;
                 ai[k] += w0 * si;

@@ -51,6 +51,20 @@ def log(msg: str) -> None:
     print(msg, flush=True)
 
 
+def stage_tol(m: int, dtype: str, sigma: float = 2.0) -> float:
+    """Gate of a stage against its numpy statement (both sides rounded).
+
+    FP64: the window phi(t) = sinh(b sqrt(m^2 - t^2)) / ... grows like
+    exp(b sqrt(m^2 - t^2)), so a rounding eps in t moves it by a relative
+    b*m*eps at worst, in the reference's closed form and in the fitted
+    polynomials alike; three such factors per term: 3 b m eps, floored at
+    1e-14.  FP32: single-precision rounding of weights and sums, 1e-6."""
+    if dtype == "c64":
+        return 1e-6
+    b = np.pi * (2.0 - 1.0 / sigma)
+    return max(1e-14, 3.0 * b * m * np.finfo(np.float64).eps)
+
+
 def rand_coeffs(N, seed):
     r = np.random.default_rng(seed)
     return r.standard_normal(tuple(N)) + 1j * r.standard_normal(tuple(N))

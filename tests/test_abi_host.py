@@ -72,6 +72,9 @@ def test_null_handling(nf):
     assert lib.nfft3_adjoint(None, None, None) == -7
     assert lib.nfft3_set_points(None, 0, None) == -7
     assert lib.nfft3_grad_points(None, None, None, None) == -7
+    assert lib.nfft3_set_tuning(None, 16, 256) == -7
+    assert lib.nfft3_get_tuning(None, None, None) == -7
+    assert lib.nfft3_autotune(None, 0, None, None, None, 1, None, None) == -7
     assert lib.nfft3_batch_trafo(-1, None, None, None, 0) == -1
     assert lib.nfft3_batch_trafo(0, None, None, None, 0) == 0
     assert lib.nfft3_strerror(-5) == b"non-finite point coordinate"

@@ -10,7 +10,7 @@ import pytest
 import oracle
 from oracle import nfft_steps as ns
 import workloads
-from gpu_common import dot_tol, log, phi0, rand_coeffs, rand_points, rel, to_dev, tol, torch_dtype
+from gpu_common import dot_tol, log, phi0, rand_coeffs, rand_points, rel, stage_tol, to_dev, tol, torch_dtype
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,68 @@ def test_stage_interp_matches_window_sum(nf, N, m, M, dtype):
     ref = ns.interpolate(g, x, m, 2.0) / phi0(m, 2.0) ** 3
     l2, li = rel(got, ref)
     assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 6, 7, 9, 10])
+def test_stage_interp_every_m(nf, m, dtype):
+    """Every window width: the stencil-read layout (row stride, rotation
+    cosets, complex<float> pair offsets) depends on 2m."""
+    N, M = (24, 20, 30), 1500
+    log(f"stage_interp N={N} m={m} M={M} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    r = np.random.default_rng(50 + m)
+    g = r.standard_normal(p.n) + 1j * r.standard_normal(p.n)
+    x = rand_points(M, 60 + m)
+    p.set_points(to_dev(x))
+    p.load_grid(to_dev(g, dtype))
+    got = p.stage_interp().cpu().numpy()
+    ref = ns.interpolate(g, x, m, 2.0) / phi0(m, 2.0) ** 3
+    l2, li = rel(got, ref)
+    assert l2 < stage_tol(m, dtype), (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("tile,items", [(8, 256), (8, 512), (16, 256), (16, 512), (32, 256), (32, 512)])
+def test_stage_interp_tunings(nf, tile, items, dtype):
+    """Every binning setting gives the same window sums (clustered and
+    uniform points, tiles cut by the grid edge)."""
+    m = 8 if dtype == "c128" else 4
+    N, M = (40, 24, 36), 6000
+    log(f"stage_interp tuning tile={tile} items={items} N={N} m={m} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_tuning(tile, items)
+    assert p.tuning() == (tile, items)
+    r = np.random.default_rng(70)
+    g = r.standard_normal(p.n) + 1j * r.standard_normal(p.n)
+    x = np.concatenate([rand_points(M // 2, 71),
+                        workloads.wrap(0.1 + 0.01 * np.random.default_rng(72).standard_normal((M - M // 2, 3)))])
+    p.set_points(to_dev(x))
+    p.load_grid(to_dev(g, dtype))
+    got = p.stage_interp().cpu().numpy()
+    ref = ns.interpolate(g, x, m, 2.0) / phi0(m, 2.0) ** 3
+    l2, li = rel(got, ref)
+    assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_autotune(nf, dtype):
+    """The autotuner picks a candidate, leaves the points set, and the
+    transform with its choice matches the direct sum."""
+    import torch
+    m = 8 if dtype == "c128" else 4
+    fh, x = workloads.smooth_uniform_case(32, 20_000)
+    p = make_plan(nf, fh.shape, m, dtype)
+    fd = to_dev(fh, dtype)
+    tile, items = p.autotune(to_dev(x), fd, reps=2)
+    log(f"autotune {dtype}: tile={tile} items={items}")
+    assert tile in (16, 32) and items in (256, 512)
+    assert p.tuning() == (tile, items) and p.M == x.shape[0]
+    got = p.trafo(fd).cpu().numpy()
+    s = workloads.sample_indices(x.shape[0], 2000, 73)
+    l2, li = rel(got[s], oracle.ndft_trafo(fh, x[s]))
+    assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype)
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
