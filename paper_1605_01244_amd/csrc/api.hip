@@ -167,7 +167,7 @@ static void free_plan(nfft3_plan_impl *p) {
     if (!p) return;
     hipFree(p->grid);
     for (void *g : p->extra_grids) hipFree(g);
-    for (int d = 0; d < 3; ++d) { hipFree(p->cdec[d]); hipFree(p->fft[d].tw); }
+    for (int d = 0; d < 3; ++d) { hipFree(p->cdec[d]); hipFree(p->fft[d].tw); hipFree(p->fft[d].stw); }
     hipFree(p->wcoef);
     free_points(p);
     hipFree(p->flag);
@@ -196,6 +196,38 @@ template <typename T>
 static int upload_real(const std::vector<double> &v, void **dst) {
     std::vector<T> h(v.begin(), v.end());
     NFFT3_HIP_TRY(hipMalloc(dst, sizeof(T) * std::max<size_t>(h.size(), 1)));
+    NFFT3_HIP_TRY(hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return NFFT3_OK;
+}
+
+template <typename T>
+static int upload_stage_twiddles(int n, void **dst) {
+    // per-stage tables of the compile-time power-of-two engine
+    const long double pi = 3.14159265358979323846264338327950288L;
+    const int size = p2_tw_size(n);
+    if (size == 0) return NFFT3_OK;
+    std::vector<T> h(2 * (size_t)size, (T)0);
+    for (int s = 1; s < p2_nrad(n); ++s) {
+        const int ns = p2_ns(n, s), R = p2_radix(n, s), off = p2_tw_offset(n, s);
+        for (int k = 0; k < ns; ++k)
+            for (int r = 0; r < R; ++r) {
+                const long long num = (long long)r * k, den = (long long)ns * R;
+                long double re, im;
+                if ((4 * num) % den == 0) {   // exact quarter points
+                    const int qd = (int)(((4 * num) / den) % 4);
+                    const long double qre[4] = {1, 0, -1, 0}, qim[4] = {0, -1, 0, 1};
+                    re = qre[qd];
+                    im = qim[qd];
+                } else {
+                    const long double a = -2.0L * pi * (long double)num / (long double)den;
+                    re = cosl(a);
+                    im = sinl(a);
+                }
+                h[2 * ((size_t)off + k * 8 + r)] = (T)re;
+                h[2 * ((size_t)off + k * 8 + r) + 1] = (T)im;
+            }
+    }
+    NFFT3_HIP_TRY(hipMalloc(dst, sizeof(T) * h.size()));
     NFFT3_HIP_TRY(hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
     return NFFT3_OK;
 }
@@ -265,6 +297,11 @@ static int build_plan(nfft3_plan_impl *p) {
         rc = f64 ? upload_twiddles<double>((int)p->n[d], &p->fft[d].tw)
                  : upload_twiddles<float>((int)p->n[d], &p->fft[d].tw);
         if (rc) return rc;
+        if (is_pow2((int)p->n[d])) {
+            rc = f64 ? upload_stage_twiddles<double>((int)p->n[d], &p->fft[d].stw)
+                     : upload_stage_twiddles<float>((int)p->n[d], &p->fft[d].stw);
+            if (rc) return rc;
+        }
     }
     std::vector<double> coef;
     const double tol = f64 ? 4e-16 : 2e-8;

@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(kBRowThreads)
 batch_rows_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ first, int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int t = batch_find(first, X, blockIdx.x);
-    rows_body<T, 0, kBRowThreads>(xf[t].rows, blockIdx.x - first[t], smem_raw);
+    rows_any<T, 0, kBRowThreads>(xf[t].rows, blockIdx.x - first[t], smem_raw);
 }
 
 template <typename T, int AXIS>
@@ -58,10 +58,10 @@ batch_cols_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ fir
     const int tile = blockIdx.x - first[t];
     if (AXIS == 1) {
         const int gx = xf[t].gx1;
-        cols_body<T, true, kBColThreads, 16>(xf[t].c1, tile % gx, tile / gx, smem_raw);
+        cols_any<T, true, kBColThreads, 16>(xf[t].c1, tile % gx, tile / gx, smem_raw);
     } else {
         const int gx = xf[t].gx0;
-        cols_body<T, true, kBColThreads, 16>(xf[t].c0, tile % gx, tile / gx, smem_raw);
+        cols_any<T, true, kBColThreads, 16>(xf[t].c0, tile % gx, tile / gx, smem_raw);
     }
 }
 

@@ -33,11 +33,65 @@ __global__ void __launch_bounds__(kColThreads) fft_cols_kernel(ColArgs a) {
     cols_body<T, FWD, kColThreads, 16>(a, blockIdx.x, blockIdx.y, smem_raw);
 }
 
+// compile-time-engine passes (power-of-two n of static_fft_len)
+template <typename T, int MODE, int N>
+__global__ void __launch_bounds__(kRowThreads) fft_rows_kernel_s(RowArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    rows_body_s<T, MODE, kRowThreads, N, static_rows_nl<T>(N)>(a, blockIdx.x, smem_raw);
+}
+
+template <typename T, bool FWD, int N>
+__global__ void __launch_bounds__(kColThreads) fft_cols_kernel_s(ColArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cols_body_s<T, FWD, kColThreads, N, static_cols_nl<T>()>(a, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+template <typename T, int MODE, int N>
+static void launch_rows_s(dim3 g, size_t lds, hipStream_t s, const RowArgs &a) {
+    hipLaunchKernelGGL((fft_rows_kernel_s<T, MODE, N>), g, dim3(kRowThreads), lds, s, a);
+}
+
+template <typename T, bool FWD, int N>
+static void launch_cols_s(dim3 g, size_t lds, hipStream_t s, const ColArgs &a) {
+    allow_lds((const void *)fft_cols_kernel_s<T, FWD, N>, lds);
+    hipLaunchKernelGGL((fft_cols_kernel_s<T, FWD, N>), g, dim3(kColThreads), lds, s, a);
+}
+
+template <typename T, int MODE>
+static bool rows_static(const RowArgs &a, dim3 g, size_t lds, hipStream_t s) {
+    if (!static_fft_len(a.n) || a.lpw != static_rows_nl<T>(a.n)) return false;
+    switch (a.n) {
+        case 64: launch_rows_s<T, MODE, 64>(g, lds, s, a); break;
+        case 128: launch_rows_s<T, MODE, 128>(g, lds, s, a); break;
+        case 256: launch_rows_s<T, MODE, 256>(g, lds, s, a); break;
+        default: launch_rows_s<T, MODE, 512>(g, lds, s, a); break;
+    }
+    return true;
+}
+
+template <typename T, bool FWD>
+static bool cols_static(const ColArgs &a, dim3 g, size_t lds, hipStream_t s) {
+    if (!static_fft_len(a.n) || a.C != static_cols_nl<T>()) return false;
+    switch (a.n) {
+        case 64: launch_cols_s<T, FWD, 64>(g, lds, s, a); break;
+        case 128: launch_cols_s<T, FWD, 128>(g, lds, s, a); break;
+        case 256: launch_cols_s<T, FWD, 256>(g, lds, s, a); break;
+        default: launch_cols_s<T, FWD, 512>(g, lds, s, a); break;
+    }
+    return true;
+}
+
 template <typename T>
 static int rows_pass(nfft3_plan_impl *p, int mode, const void *in, void *out, int deriv) {
     RowArgs a = make_row_args<T>(p, in, out, deriv, kRowThreads);
     const int64_t nblk = row_blocks(p, a);
     const size_t lds = row_lds<T>(a);
+    const bool done = mode == 0 ? rows_static<T, 0>(a, dim3((unsigned)nblk), lds, p->stream)
+                                : rows_static<T, 1>(a, dim3((unsigned)nblk), lds, p->stream);
+    if (done) {
+        NFFT3_LAUNCH_CHECK("fft_rows_kernel_s");
+        return NFFT3_OK;
+    }
     if (mode == 0)
         hipLaunchKernelGGL((fft_rows_kernel<T, 0>), dim3((unsigned)nblk), dim3(kRowThreads), lds, p->stream, a);
     else
@@ -52,6 +106,12 @@ static int cols_pass(nfft3_plan_impl *p, int axis, bool fwd, int Lin, int Lout, 
     ColArgs a = make_col_args<T>(p, p->grid, axis, Lin, Lout, s_outer, kColThreads, 16);
     dim3 grid((unsigned)col_grid_x(a), (unsigned)n_outer);
     const size_t lds = col_lds<T>(a);
+    const bool done = fwd ? cols_static<T, true>(a, grid, lds, p->stream)
+                          : cols_static<T, false>(a, grid, lds, p->stream);
+    if (done) {
+        NFFT3_LAUNCH_CHECK("fft_cols_kernel_s");
+        return NFFT3_OK;
+    }
     if (fwd) {
         allow_lds((const void *)fft_cols_kernel<T, true>, lds);
         hipLaunchKernelGGL((fft_cols_kernel<T, true>), grid, dim3(kColThreads), lds, p->stream, a);

@@ -204,6 +204,78 @@ __device__ __forceinline__ void fft_lines(c_t<T> *buf, int ls, int nlines, int n
     fft_stage_r<T, VMAX, NT, FWD, LINE_FAST, false, true>(rl.r[rl.nrad - 1], buf, ls, nlines, n, Ns, tw, ld, st);
 }
 
+// ------------------------------------ compile-time power-of-two engine ----
+// The same Stockham stages with n, the radices (p2_radix), the spans Ns, the
+// lines per workgroup NL and the LDS line stride LS known at compile time:
+// the index math reduces to shifts and masks, and a stage's twiddles come
+// from its own table (8 entries per k, so one butterfly's are contiguous).
+template <typename T, int N, int S, int NL, int LS, int NT, bool FWD, bool LINE_FAST, class LD, class ST>
+__device__ __forceinline__ void sfft_stage(c_t<T> *buf, const c_t<T> *__restrict__ stw, LD &ld, ST &st) {
+    constexpr int R = p2_radix(N, S), NS = p2_ns(N, S), NRAD = p2_nrad(N);
+    constexpr bool FIRST = S == 0, LAST = S == NRAD - 1;
+    constexpr int NBL = N / R, NB = NL * NBL, BPT = (NB + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    c_t<T> v[BPT][R];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int bt = tid + i * NT;
+        if (NB % NT == 0 || bt < NB) {
+            const int j = LINE_FAST ? bt / NL : bt % NBL;
+            const int line = LINE_FAST ? bt % NL : bt / NBL;
+            if constexpr (FIRST) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = ld(line, j + r * NBL);
+            } else {
+                const c_t<T> *src = buf + line * LS + j;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = src[r * NBL];
+            }
+        }
+    }
+    if constexpr (!FIRST && !LAST) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int bt = tid + i * NT;
+        if (NB % NT == 0 || bt < NB) {
+            const int j = LINE_FAST ? bt / NL : bt % NBL;
+            const int line = LINE_FAST ? bt % NL : bt / NBL;
+            const int k = j & (NS - 1);
+            if constexpr (!FIRST) {
+                const c_t<T> *w = stw + p2_tw_offset(N, S) + k * 8;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = FWD ? cmul(v[i][r], w[r]) : cmulc(v[i][r], w[r]);
+            }
+            dft_small<T, R, FWD>(v[i]);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) st(line, j + r * NBL, v[i][r]);
+            } else {
+                c_t<T> *dst = buf + line * LS + (j - k) * R + k;   // (j / Ns) Ns R + j mod Ns
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[r * NS] = v[i][r];
+            }
+        }
+    }
+    if constexpr (!LAST) __syncthreads();
+}
+
+template <typename T, int N, int S, int NL, int LS, int NT, bool FWD, bool LINE_FAST, class LD, class ST>
+__device__ __forceinline__ void sfft_lines(c_t<T> *buf, const c_t<T> *__restrict__ stw, LD &ld, ST &st) {
+    sfft_stage<T, N, S, NL, LS, NT, FWD, LINE_FAST>(buf, stw, ld, st);
+    if constexpr (S + 1 < p2_nrad(N)) sfft_lines<T, N, S + 1, NL, LS, NT, FWD, LINE_FAST>(buf, stw, ld, st);
+}
+
+// Power-of-two lengths served by the compile-time engine, and its lines per
+// workgroup: rows fill 32 KiB of LDS (as make_row_args), column tiles are
+// 128-byte segments (as make_col_args).
+constexpr bool static_fft_len(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
+template <typename T>
+constexpr int static_rows_nl(int n) {
+    return 32768 / (n * (int)sizeof(c_t<T>)) < 64 ? 32768 / (n * (int)sizeof(c_t<T>)) : 64;
+}
+template <typename T>
+constexpr int static_cols_nl() { return 128 / (int)sizeof(c_t<T>); }
+
 // FFT position -> compact index of a pruned line of L entries (frequency
 // k = pos or pos - n; kept when -L/2 <= k < L/2), or -1.
 __device__ __forceinline__ int compact_of(int pos, int L, int n) {
@@ -222,6 +294,7 @@ struct RowArgs {
     void *out;
     const void *c0, *c1, *c2;
     const void *tw;
+    const void *stw;             // stage tables of the compile-time engine
     int n, N0, N1, N2;
     int64_t grid_s0, grid_s1;   // grid strides of i0, i1 (elements)
     int lpw;                     // rows per workgroup
@@ -290,6 +363,68 @@ __device__ __forceinline__ void rows_body(const RowArgs &a, int blk, unsigned ch
     }
 }
 
+// Row pass with the compile-time engine: n = N, NL rows per workgroup (the
+// last workgroup may hold fewer: the others are masked).
+template <typename T, int MODE, int NT, int N, int NL>
+__device__ __forceinline__ void rows_body_s(const RowArgs &a, int blk, unsigned char *smem_raw) {
+    c_t<T> *buf = reinterpret_cast<c_t<T> *>(smem_raw);
+    const int nrows = a.N0 * a.N1;
+    const int rbase = blk * NL;
+    const int nl = min(NL, nrows - rbase);
+    const T *c0 = (const T *)a.c0, *c1 = (const T *)a.c1, *c2 = (const T *)a.c2;
+    const T twopi = (T)6.283185307179586476925286766559;
+    const int N0 = a.N0, N1 = a.N1, N2 = a.N2, deriv = a.deriv;
+    const int s0 = (int)a.grid_s0, s1 = (int)a.grid_s1;
+    const c_t<T> *stw = (const c_t<T> *)a.stw;
+    if (MODE == 0) {
+        const c_t<T> *fhat = (const c_t<T> *)a.in;
+        c_t<T> *grid = (c_t<T> *)a.out;
+        auto ld = [&](int line, int pos) -> c_t<T> {
+            const int i2 = compact_of(pos, N2, N);
+            if (i2 < 0 || line >= nl) return cmk<T>(0, 0);
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            c_t<T> v = fhat[(int64_t)row * N2 + i2];
+            const T s = c0[i0] * c1[i1] * c2[i2];
+            v.x *= s;
+            v.y *= s;
+            if (deriv >= 0) {   // times -2 pi i k_d
+                const int kd = deriv == 0 ? i0 - N0 / 2 : deriv == 1 ? i1 - N1 / 2 : i2 - N2 / 2;
+                const T f = twopi * (T)kd;
+                v = cmk<T>(f * v.y, -f * v.x);
+            }
+            return v;
+        };
+        auto st = [&](int line, int pos, c_t<T> v) {
+            if (line >= nl) return;
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            grid[(int64_t)i0 * s0 + i1 * s1 + pos] = v;
+        };
+        sfft_lines<T, N, 0, NL, N, NT, true, false>(buf, stw, ld, st);
+    } else {
+        const c_t<T> *grid = (const c_t<T> *)a.in;
+        c_t<T> *fhat = (c_t<T> *)a.out;
+        auto ld = [&](int line, int pos) -> c_t<T> {
+            if (line >= nl) return cmk<T>(0, 0);
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            return grid[(int64_t)i0 * s0 + i1 * s1 + pos];
+        };
+        auto st = [&](int line, int pos, c_t<T> v) {
+            const int o = compact_of(pos, N2, N);
+            if (o < 0 || line >= nl) return;
+            const int row = rbase + line;
+            const int i0 = row / N1, i1 = row - i0 * N1;
+            const T s = c0[i0] * c1[i1] * c2[o];
+            v.x *= s;
+            v.y *= s;
+            fhat[(int64_t)row * N2 + o] = v;
+        };
+        sfft_lines<T, N, 0, NL, N, NT, false, false>(buf, stw, ld, st);
+    }
+}
+
 // ----------------------------------------------------- column passes ----
 // In-place transform along a strided axis of tiles of C adjacent columns.
 // Column c of tile (outer, x0) has element i at
@@ -299,6 +434,7 @@ __device__ __forceinline__ void rows_body(const RowArgs &a, int blk, unsigned ch
 struct ColArgs {
     void *data;
     const void *tw;
+    const void *stw;
     int n, Lin, Lout;
     int ncols;          // contiguous extent (columns)
     int C;              // columns per tile
@@ -337,6 +473,65 @@ __device__ __forceinline__ void cols_body(const ColArgs &a, int bx, int by, unsi
     fft_lines<T, VMAX, NT, FWD, true>(buf, ls, C, n, a.rl, (const c_t<T> *)a.tw, ld, st);
 }
 
+
+// Column pass with the compile-time engine: n = N, C = NC columns per tile.
+template <typename T, bool FWD, int NT, int N, int NC>
+__device__ __forceinline__ void cols_body_s(const ColArgs &a, int bx, int by, unsigned char *smem_raw) {
+    c_t<T> *buf = reinterpret_cast<c_t<T> *>(smem_raw);
+    const int x0 = bx * NC;
+    const int nc = min(NC, a.ncols - x0);
+    c_t<T> *data = (c_t<T> *)a.data + (int64_t)by * a.s_outer + x0;
+    const int Lin = a.Lin, Lout = a.Lout;
+    const int64_t sa = a.s_axis;
+    auto ld = [&](int c, int pos) -> c_t<T> {
+        if (c >= nc) return cmk<T>(0, 0);
+        int i = pos;
+        if (Lin < N) {
+            i = compact_of(pos, Lin, N);
+            if (i < 0) return cmk<T>(0, 0);
+        }
+        return data[(int64_t)i * sa + c];
+    };
+    auto st = [&](int c, int pos, c_t<T> v) {
+        if (c >= nc) return;
+        int o = pos;
+        if (Lout < N) {
+            o = compact_of(pos, Lout, N);
+            if (o < 0) return;
+        }
+        data[(int64_t)o * sa + c] = v;
+    };
+    sfft_lines<T, N, 0, NC, N + 1, NT, FWD, true>(buf, (const c_t<T> *)a.stw, ld, st);
+}
+
+// Pass bodies that take the compile-time engine when it serves (n, lines) and
+// the generic one otherwise (a uniform branch per workgroup; used where one
+// kernel covers transforms of several sizes).
+template <typename T, int MODE, int NT>
+__device__ __forceinline__ void rows_any(const RowArgs &a, int blk, unsigned char *smem_raw) {
+    if (static_fft_len(a.n) && a.lpw == static_rows_nl<T>(a.n)) {
+        switch (a.n) {
+            case 64: rows_body_s<T, MODE, NT, 64, static_rows_nl<T>(64)>(a, blk, smem_raw); return;
+            case 128: rows_body_s<T, MODE, NT, 128, static_rows_nl<T>(128)>(a, blk, smem_raw); return;
+            case 256: rows_body_s<T, MODE, NT, 256, static_rows_nl<T>(256)>(a, blk, smem_raw); return;
+            default: rows_body_s<T, MODE, NT, 512, static_rows_nl<T>(512)>(a, blk, smem_raw); return;
+        }
+    }
+    rows_body<T, MODE, NT>(a, blk, smem_raw);
+}
+
+template <typename T, bool FWD, int NT, int VMAX>
+__device__ __forceinline__ void cols_any(const ColArgs &a, int bx, int by, unsigned char *smem_raw) {
+    if (static_fft_len(a.n) && a.C == static_cols_nl<T>()) {
+        switch (a.n) {
+            case 64: cols_body_s<T, FWD, NT, 64, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
+            case 128: cols_body_s<T, FWD, NT, 128, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
+            case 256: cols_body_s<T, FWD, NT, 256, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
+            default: cols_body_s<T, FWD, NT, 512, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
+        }
+    }
+    cols_body<T, FWD, NT, VMAX>(a, bx, by, smem_raw);
+}
 
 // Largest number of lines such that every stage fits VMAX values per thread.
 inline int lines_fit(const FftAxisPlan &f, int vmax, int cap, int nthreads) {
@@ -377,6 +572,7 @@ inline RowArgs make_row_args(const nfft3_plan_impl *p, const void *in, void *out
     a.c1 = p->cdec[1];
     a.c2 = p->cdec[2];
     a.tw = f.tw;
+    a.stw = f.stw;
     a.n = f.n;
     a.N0 = (int)p->N[0];
     a.N1 = (int)p->N[1];
@@ -404,6 +600,7 @@ inline ColArgs make_col_args(const nfft3_plan_impl *p, void *grid, int axis, int
     ColArgs a;
     a.data = grid;
     a.tw = f.tw;
+    a.stw = f.stw;
     a.n = f.n;
     a.Lin = Lin;
     a.Lout = Lout;

@@ -58,7 +58,35 @@ struct FftAxisPlan {
     int nrad = 0;             // number of radix stages
     int radix[16] = {0};      // radices in application order
     void *tw = nullptr;       // device twiddles exp(-2 pi i k/n), k = 0..n-1 (c_t<T>)
+    void *stw = nullptr;      // power-of-two n: per-stage twiddle tables (p2_tw_offset)
 };
+
+// Compile-time radix plan of a power-of-two length n = 2^l: floor(l/3)
+// radix-8 stages, then one radix-2 or radix-4 stage for l mod 3 = 1 or 2.
+constexpr int p2_log(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+constexpr int p2_nrad(int n) { return p2_log(n) / 3 + (p2_log(n) % 3 ? 1 : 0); }
+constexpr int p2_radix(int n, int s) {
+    return s < p2_log(n) / 3 ? 8 : (p2_log(n) % 3 == 1 ? 2 : 4);
+}
+// product of the radices before stage s (the Stockham span Ns)
+constexpr int p2_ns(int n, int s) {
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= p2_radix(n, i);
+    return ns;
+}
+// Stage s >= 1 twiddles: entry [k * 8 + r] = exp(-2 pi i r k / (Ns R)),
+// k < Ns, r < R; this is the offset of stage s's table.
+constexpr int p2_tw_offset(int n, int s) {
+    int off = 0;
+    for (int i = 1; i < s; ++i) off += p2_ns(n, i) * 8;
+    return off;
+}
+constexpr int p2_tw_size(int n) { return p2_tw_offset(n, p2_nrad(n)); }
 
 // Points are sorted by (tile, z-cell); a tile is By x Bx cells of the (y, x)
 // plane.  Work items for the window-sum kernels are at most Subproblems::maxpts
