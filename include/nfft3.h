@@ -143,8 +143,8 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_
  * setting, only faster or slower) ---------------------------------------- */
 
 /* tile: edge, in grid cells, of the (y, x) tiles the points are binned into
- * (8, 16 or 32; the plane a work group stages in LDS is the tile plus the
- * 2m-1 halo).  items: points per work item of the window-sum kernels (256
+ * (a multiple of 4 from 8 to 32; the plane a work group stages in LDS is the
+ * tile plus the 2m-1 halo).  items: points per work item of the window-sum kernels (256
  * or 512).  0 keeps the current value.  Defaults: tile 32, items 512.  A changed setting drops the plan's
  * points: call nfft3_set_points again.  INVALID_ARG for other values. */
 int nfft3_set_tuning(nfft3_plan_t p, int tile, int items);

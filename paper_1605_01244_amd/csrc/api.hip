@@ -257,11 +257,11 @@ static int upload_twiddles(int n, void **dst) {
     return NFFT3_OK;
 }
 
-// Point tiles of edge T (a power of two <= kMaxTile whose plane, tile +
-// stencil halo, fits the window-sum kernels' staging of kMaxPlane elements)
-// and the binning buffers sized for them.
+// Point tiles of edge T (at most kMaxTile, and small enough that the plane,
+// tile + stencil halo, fits the window-sum kernels' staging of kMaxPlane
+// elements) and the binning buffers sized for them.
 static int alloc_bins(nfft3_plan_impl *p, int T) {
-    while (T > 1 && (T + 2 * p->m - 1) * (T + 2 * p->m - 1) > kMaxPlane) T /= 2;
+    while (T > 4 && (T + 2 * p->m - 1) * (T + 2 * p->m - 1) > kMaxPlane) T -= 4;
     free_bins(p);
     p->bins.By = (int)std::min<int64_t>(T, p->n[1]);
     p->bins.Bx = (int)std::min<int64_t>(T, p->n[2]);
@@ -477,7 +477,7 @@ const char *nfft3_last_hip_error(void) { return g_last_hip.c_str(); }
 
 int nfft3_set_tuning(nfft3_plan_t p, int tile, int items) {
     if (!p) return NFFT3_ERR_NULL;
-    if (tile != 0 && tile != 8 && tile != 16 && tile != 32) return NFFT3_ERR_INVALID_ARG;
+    if (tile != 0 && (tile < 8 || tile > kMaxTile || tile % 4 != 0)) return NFFT3_ERR_INVALID_ARG;
     if (items != 0 && items != kItemPts && items != 2 * kItemPts) return NFFT3_ERR_INVALID_ARG;
     int cur_tile = 0, cur_items = 0;
     nfft3_get_tuning(p, &cur_tile, &cur_items);
@@ -507,7 +507,7 @@ int nfft3_autotune(nfft3_plan_t p, int64_t M, const double *x, const void *fhat,
     if (!p) return NFFT3_ERR_NULL;
     if (!fhat || (M > 0 && (!x || !f))) return NFFT3_ERR_NULL;
     if (reps < 1) return NFFT3_ERR_INVALID_ARG;
-    const int tiles[] = {16, 32};
+    const int tiles[] = {16, 24, 32};
     const int items[] = {kItemPts, 2 * kItemPts};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     NFFT3_HIP_TRY(hipEventCreate(&e0));
