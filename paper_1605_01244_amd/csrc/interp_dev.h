@@ -240,6 +240,10 @@ template <> struct LdsUnit<float> {
 
 constexpr int cgcd(int a, int b) { return b ? cgcd(b, a % b) : a; }
 
+// 0: every item walks up; 1: odd items walk down; 2: odd items longer than
+// 3 window widths walk down
+constexpr int kInterpWalk = 1;
+
 // largest divisor of n that is at most 7 (a chunk of stencil-row reads)
 constexpr int row_chunk(int n) {
     for (int c = 7; c > 1; --c)
@@ -281,6 +285,15 @@ __device__ __forceinline__ void rotate_rows(T *w, int t) {
 #pragma unroll
         for (int j = 0; j < W; ++j) w[j] = tmp[j];
     }
+}
+
+// Direction of an item's walk over its planes.  Consecutive items of a tile
+// column overlap in the 2m-1 planes at the top of one and the bottom of the
+// next, and are dispatched together (see xcd_item): walking them in opposite
+// directions makes both read the shared planes at about the same time, so
+// the second read can hit in L2.
+__device__ __forceinline__ bool interp_walk_down(int item, int nplanes, int W) {
+    return kInterpWalk == 1 ? (item & 1) != 0 : kInterpWalk == 2 ? ((item & 1) != 0 && nplanes > 3 * W) : false;
 }
 
 // Point slot k of thread t is sorted index item.y + k*256 + t: each slot's
@@ -391,27 +404,31 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
     constexpr bool kDirect = EPU == 1 && W == 16;
     vec2_t<T> stage[kDirect ? 1 : NF];
     const int plane_bytes = (int)(plane * (int64_t)sizeof(c_t<T>));
+    // plane order: see interp_walk_down
+    const bool down = interp_walk_down(item_index, it.nplanes, W);
+    const int np = it.nplanes;
     if constexpr (kDirect) {
-        ps_fetch_lds<NF>((const c_t<double> *)grid + (int64_t)wrapi(it.zbeg, a.n0) * plane, plane_bytes, it, off,
-                         (c_t<double> *)buf0);
+        ps_fetch_lds<NF>((const c_t<double> *)grid + (int64_t)wrapi(it.zbeg + (down ? np - 1 : 0), a.n0) * plane,
+                         plane_bytes, it, off, (c_t<double> *)buf0);
         __builtin_amdgcn_s_waitcnt(0);
     } else {
-        ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
+        ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg + (down ? np - 1 : 0), a.n0) * plane, stage);
         ps_store<T, NF>(buf0, it, lidx, stage);
     }
     __syncthreads();
 
-    for (int i = 0; i < it.nplanes; ++i) {
-        const bool more = i + 1 < it.nplanes;
+    for (int st = 0; st < np; ++st) {
+        const int i = down ? np - 1 - st : st;      // plane index of this step
+        const bool more = st + 1 < np;
         if (more) {
-            const int64_t zoff = (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane;
+            const int64_t zoff = (int64_t)wrapi(it.zbeg + (down ? i - 1 : i + 1), a.n0) * plane;
             if constexpr (kDirect)
                 ps_fetch_lds<NF>((const c_t<double> *)grid + zoff, plane_bytes, it, off,
-                                 (c_t<double> *)((i & 1) ? buf0 : buf1));
+                                 (c_t<double> *)((st & 1) ? buf0 : buf1));
             else
                 ps_fetch<T, NF>(grid, off, zoff, stage);
         }
-        const U *pl = reinterpret_cast<const U *>((i & 1) ? buf1 : buf0);
+        const U *pl = reinterpret_cast<const U *>((st & 1) ? buf1 : buf0);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int r0 = i - zlo[k];
@@ -474,7 +491,7 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
         if constexpr (kDirect) {
             __builtin_amdgcn_s_waitcnt(0);
         } else {
-            if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, lidx, stage);
+            if (more) ps_store<T, NF>((st & 1) ? buf0 : buf1, it, lidx, stage);
         }
         __syncthreads();
     }
