@@ -33,6 +33,38 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sources of the window-sum kernel whose HBM traffic profiles/ records; the
+# recorded traffic is reported only while these files are unchanged.
+TRAFFIC_SOURCES = ["paper_1605_01244_amd/csrc/interp_dev.h", "paper_1605_01244_amd/csrc/interp.hip",
+                   "paper_1605_01244_amd/csrc/internal.h"]
+TRAFFIC_PROFILE = "profiles/interp_window_sums_N256_M1e7_traffic.md"
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fp:
+            h.update(fp.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(form):
+    """HBM bytes per launch of the window-sum kernel from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when it is
+    missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-data:"):
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel_sources_sha256") != kernel_sources_sha():
+                return None
+            return rec.get(form, {}).get("bytes_per_launch")
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,7 +213,8 @@ def main():
                                f"{main_form} m={r['m']}; points set once, step = trafo",
                    "N": N, "M": M, "sigma": 2.0, "m": r["m"], "parallelism": "single GPU"},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(main_form) if dom.startswith("interp") else None,
                      "alg_bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom},
         "cpu_baseline": cpu,
         "forms": {},
