@@ -80,7 +80,79 @@ def parse():
     ap.add_argument("--forms", default="fp32,fp64")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint / point-gradient / batched / autograd measurements")
     return ap.parse_args()
+
+
+def bench_batched(nf, torch, dev, workloads, stream):
+    """64 coefficient sets of N in {64, 96, 128}^3 with lognormal point
+    counts, each with its three derivative fields: one nfft3_batch_trafo per
+    form (four launches over all 256 transforms), timed with HIP events."""
+    t0 = time.time()
+    sets = workloads.batched_sets(64)
+    log(f"batched inputs generated in {time.time() - t0:.1f}s")
+    res = {"workload": "64 sets, N in {64,96,128}^3, M_t lognormal in [1e4,1e6] (total "
+                       f"{sum(s[2].shape[0] for s in sets)}), field + 3 derivative fields each, sigma=2"}
+    for form, dt, m in (("fp32", torch.complex64, 4), ("fp64", torch.complex128, 8)):
+        plans, fh = [], []
+        for N, f, x in sets:
+            p = nf.Plan((N, N, N), m=m, dtype=dt, device=dev)
+            p.set_points(torch.from_numpy(x).to(dev))
+            plans.append(p)
+            fh.append(torch.from_numpy(f).to(dev).to(dt))
+        nf.batch_trafo(plans, fh, 7)
+        torch.cuda.synchronize()
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            outs = nf.batch_trafo(plans, fh, 7)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        evals = 4 * sum(p.M for p in plans)
+        res[form] = {"m": m, "ms_per_batch": ms, "point_evaluations_per_s": evals / (ms * 1e-3)}
+        log(f"batched {form}: {ms:.2f} ms per batch of 256 transforms ({evals / ms * 1e3:.3e} evaluations/s)")
+        for p in plans:
+            p.close()
+        del plans, fh, outs
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_autograd(nf, torch, dev, workloads):
+    """Differentiation form: N = 128^3, M = 1e6 clustered points; forward
+    (set_points + trafo) and backward (adjoint + point gradient) of
+    L = sum Re(conj(w) f), wall time per step on the device clock."""
+    fhat, x, w = workloads.clustered_grad_case(128, 1_000_000)
+    res = {"workload": "N=128^3, M=1e6 points in 16 clusters std 0.02, L = sum Re(conj(w) f)"}
+    for form, dt, m in (("fp32", torch.complex64, 4), ("fp64", torch.complex128, 8)):
+        plan = nf.Plan(fhat.shape, m=m, dtype=dt, device=dev)
+        fh = torch.from_numpy(fhat).to(dev).to(dt).requires_grad_(True)
+        xd = torch.from_numpy(x).to(dev).requires_grad_(True)
+        wd = torch.from_numpy(w).to(dev).to(dt)
+
+        def step():
+            fh.grad = None
+            xd.grad = None
+            f = nf.type2(fh, xd, plan)
+            (torch.conj(wd) * f).real.sum().backward()
+
+        step()
+        torch.cuda.synchronize()
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[form] = {"m": m, "ms_forward_backward": ms}
+        log(f"autograd {form}: {ms:.2f} ms per forward+backward")
+        plan.close()
+    return res
 
 
 def main():
@@ -156,14 +228,43 @@ def main():
         torch.cuda.synchronize()
         ms_grid = ga.elapsed_time(gb) / args.steps
         ms_interp = ia.elapsed_time(ib) / args.steps
+        extra = {}
+        if not args.no_extras:
+            # adjoint (type-1: spread + adjoint FFT passes + truncate) and the
+            # point gradient on the same plan and points
+            G = out.clone()
+            adj = torch.empty_like(fhd)
+            reps = max(1, args.steps // 2)
+            plan.adjoint(G, out=adj)
+            aa, ab = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            aa.record(stream)
+            for _ in range(reps):
+                plan.adjoint(G, out=adj)
+            ab.record(stream)
+            plan.grad_points(fhd, G)
+            qa, qb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            qa.record(stream)
+            for _ in range(reps):
+                gx = plan.grad_points(fhd, G)
+            qb.record(stream)
+            torch.cuda.synchronize()
+            extra = {"adjoint_ms": aa.elapsed_time(ab) / reps, "grad_points_ms": qa.elapsed_time(qb) / reps}
+            del G, adj, gx
         f = out[torch.from_numpy(sample).to(dev)].cpu().numpy() if len(sample) else None
         results[form] = dict(m=m, dtype=dt, ms_step=ms_step, wall_s=wall, t_set=t_set, ms_grid=ms_grid,
-                             ms_interp=ms_interp, f_sample=f, n=plan.n, tuning=plan.tuning())
+                             ms_interp=ms_interp, f_sample=f, n=plan.n, tuning=plan.tuning(), extra=extra)
         log(f"{form} m={m}: {ms_step:.3f} ms/step ({M / ms_step * 1e3:.3e} pts/s); grid stage {ms_grid:.3f} ms, "
             f"interp stage {ms_interp:.3f} ms; set_points {t_set * 1e3:.1f} ms")
         plan.close()
         del plan
         torch.cuda.empty_cache()
+
+    extras = {}
+    if not args.no_extras:
+        del x_d, fh32, fh64
+        torch.cuda.empty_cache()
+        extras["batched"] = bench_batched(nf, torch, dev, workloads, stream)
+        extras["autograd"] = bench_autograd(nf, torch, dev, workloads)
 
     # CPU baseline = the oracle on the seeded sample (also the error reference)
     cpu = None
@@ -224,9 +325,11 @@ def main():
             "m": rr["m"], "points_per_s": M / (rr["ms_step"] * 1e-3), "ms_per_step": rr["ms_step"],
             "ms_grid_stage": rr["ms_grid"], "ms_interp_stage": rr["ms_interp"],
             "set_points_ms": rr["t_set"] * 1e3, "wall_s_timed": rr["wall_s"],
-            "tile": rr["tuning"][0], "points_per_item": rr["tuning"][1],
+            "tile": rr["tuning"][0], "points_per_item": rr["tuning"][1], **rr["extra"],
             "rel_l2": errs.get(form, (None, None))[0], "rel_linf": errs.get(form, (None, None))[1],
         }
+    if extras:
+        line["extras"] = extras
     print(json.dumps(line), flush=True)
 
 
