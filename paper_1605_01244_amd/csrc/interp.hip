@@ -16,7 +16,8 @@
 // the plane inside its stencil adds w0 * sum_{r1,r2} w1 w2 g from LDS; the y/x
 // weights live in registers for the whole item, the z weight is one polynomial
 // per plane.  The spread kernel accumulates each plane in LDS with LDS atomics
-// and flushes it to the grid with global atomics.
+// (64-bit fixed point, see spread_ps_kernel) and flushes it to the grid with
+// global atomics.
 #include "interp_dev.h"
 
 namespace nfft3 {
@@ -116,20 +117,32 @@ __global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
 }
 
 // ------------------------------------------------------------ spread ----
+// The plane accumulator in LDS holds 64-bit fixed-point values: on gfx950 an
+// LDS float atomic add runs ~15x slower than an LDS 64-bit integer atomic
+// add (measured), whatever the address pattern.  A chunk of at most 256
+// points is accumulated at scale 2^k with 2^k max|f| < 2^53, so every
+// contribution |f w0 w1 w2| 2^k (window values <= 1) is below 2^53 and any
+// sum of at most 256 of them stays below 2^61; a contribution is rounded to
+// the nearest integer, an error of at most 2^-54 max|f| (half an FP64 ulp of
+// the chunk's largest value).  Each flushed plane is converted back (exact
+// power-of-two scaling) and added to the grid with global atomics.
+__device__ __forceinline__ long long fixed_round(double x) { return __double2ll_rn(x); }
+
 template <typename T, int W>
 __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     constexpr int m = W / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ float wmax[kPsThreads / 64];
     const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
     for (int lo = item.y; lo < item.z; lo += kPsThreads) {
     __syncthreads();
     const PSItem it = ps_range(a, m, item.x, lo, min(item.z, lo + kPsThreads));
-    c_t<T> *acc = reinterpret_cast<c_t<T> *>(smem_raw);
-    T *scoef = reinterpret_cast<T *>(acc + it.psz);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);   // (re, im) per element
+    T *scoef = reinterpret_cast<T *>(acc + 2 * it.psz);
     const T *coef = (const T *)a.coef;
     const int nc = W * (a.deg + 1);
     for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
-    for (int e = threadIdx.x; e < it.psz; e += kPsThreads) acc[e] = cmk<T>(0, 0);
+    for (int e = threadIdx.x; e < 2 * it.psz; e += kPsThreads) acc[e] = 0ull;
 
     T w1[W], w2[W];
     T f0 = 0;
@@ -147,6 +160,10 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         window_weights<T, W>(f2, coef, a.deg, w2);
         v = ((const c_t<T> *)a.vals)[a.perm[it.p]];
     }
+    // chunk scale 2^k: 2^k max|f| < 2^53
+    float amax = it.active ? (float)fmax(fabs((double)v.x), fabs((double)v.y)) : 0.f;
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
     const int zlo = zc - m + 1 - it.zbeg;
     constexpr int NF = ps_nf<W>();
     int off[NF], lidx[NF];
@@ -154,20 +171,30 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     c_t<T> *grid = (c_t<T> *)a.grid_out;
     const int64_t plane = (int64_t)a.n1 * a.n2;
     __syncthreads();
+    float bmax = 0.f;
+#pragma unroll
+    for (int w = 0; w < kPsThreads / 64; ++w) bmax = fmaxf(bmax, wmax[w]);
+    int ex = 0;
+    if (bmax > 0.f) frexpf(bmax * 1.0001f, &ex);   // bmax < 2^ex (float rounding of |f| covered)
+    const int k = 52 - ex;
+    const double vr0 = ldexp((double)v.x, k), vi0 = ldexp((double)v.y, k);
+    double w2d[W];
+#pragma unroll
+    for (int r = 0; r < W; ++r) w2d[r] = (double)w2[r];
 
     for (int i = 0; i < it.nplanes; ++i) {
         const int r0 = i - zlo;
         if (it.active && r0 >= 0 && r0 < W) {
-            const T w0 = piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0);
-            const T vr = w0 * v.x, vi = w0 * v.y;
-            c_t<T> *base = acc + yo * it.PX + xo;
+            const double w0 = (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0);
+            const double vr = w0 * vr0, vi = w0 * vi0;
+            unsigned long long *base = acc + 2 * (yo * it.PX + xo);
             for (int r1 = 0; r1 < W; ++r1) {
-                c_t<T> *row = base + r1 * it.PX;
-                const T br = w1[r1] * vr, bi = w1[r1] * vi;
+                unsigned long long *row = base + 2 * r1 * it.PX;
+                const double br = (double)w1[r1] * vr, bi = (double)w1[r1] * vi;
 #pragma unroll
                 for (int r2 = 0; r2 < W; ++r2) {
-                    atomicAdd(&row[r2].x, w2[r2] * br);
-                    atomicAdd(&row[r2].y, w2[r2] * bi);
+                    atomicAdd(&row[2 * r2], (unsigned long long)fixed_round(w2d[r2] * br));
+                    atomicAdd(&row[2 * r2 + 1], (unsigned long long)fixed_round(w2d[r2] * bi));
                 }
             }
         }
@@ -175,14 +202,15 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         // flush this plane to the grid and clear it
         const int64_t zoff = (int64_t)wrapi(it.zbeg + i, a.n0) * plane;
 #pragma unroll
-        for (int k = 0; k < NF; ++k) {
-            const int e = threadIdx.x + k * kPsThreads;
+        for (int kk = 0; kk < NF; ++kk) {
+            const int e = threadIdx.x + kk * kPsThreads;
             if (e < it.psz) {
-                const c_t<T> s = acc[e];
-                if (s.x != (T)0 || s.y != (T)0) {
-                    unsafeAtomicAdd(&grid[zoff + off[k]].x, s.x);
-                    unsafeAtomicAdd(&grid[zoff + off[k]].y, s.y);
-                    acc[e] = cmk<T>(0, 0);
+                const long long sr = (long long)acc[2 * e], si = (long long)acc[2 * e + 1];
+                if (sr != 0 || si != 0) {
+                    unsafeAtomicAdd(&grid[zoff + off[kk]].x, (T)ldexp((double)sr, -k));
+                    unsafeAtomicAdd(&grid[zoff + off[kk]].y, (T)ldexp((double)si, -k));
+                    acc[2 * e] = 0ull;
+                    acc[2 * e + 1] = 0ull;
                 }
             }
         }
@@ -236,7 +264,9 @@ static int spread_w(nfft3_plan_impl *p, const void *f, void *grid) {
     PSArgs a = ps_args(p);
     a.vals = f;
     a.grid_out = grid;
-    const size_t lds = ps_lds(p, 1);
+    // 16 bytes (two 64-bit fixed-point values) per staged element + the coefficients
+    const size_t psz = (size_t)(p->bins.By + W - 1) * (p->bins.Bx + W - 1);
+    const size_t lds = psz * 16 + (size_t)W * (p->deg + 1) * sizeof(T);
     allow_lds((const void *)spread_ps_kernel<T, W>, lds);
     hipLaunchKernelGGL((spread_ps_kernel<T, W>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds, p->stream, a);
     NFFT3_LAUNCH_CHECK("spread_ps_kernel");
