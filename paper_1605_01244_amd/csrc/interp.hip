@@ -29,90 +29,17 @@ __global__ void __launch_bounds__(kPsThreads) interp_ps_kernel(PSArgs a) {
 }
 
 // ------------------------------------------------------------- grad ----
+// The interp body in its derivative mode (rotated, conflict-free reads), one
+// point per thread: items of more points are taken 256 at a time.
 template <typename T, int W>
-__global__ void __launch_bounds__(kPsThreads) grad_ps_kernel(PSArgs a) {
-    constexpr int m = W / 2;
+__global__ void __launch_bounds__(kPsThreads) __attribute__((amdgpu_waves_per_eu(2)))
+grad_ps_kernel(PSArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
-    // items may hold more points than threads: take them 256 at a time
+    const int idx = xcd_item(blockIdx.x, gridDim.x);
+    const int4 item = a.items[idx];
     for (int lo = item.y; lo < item.z; lo += kPsThreads) {
-    __syncthreads();
-    const PSItem it = ps_range(a, m, item.x, lo, min(item.z, lo + kPsThreads));
-    c_t<T> *buf0 = reinterpret_cast<c_t<T> *>(smem_raw);
-    c_t<T> *buf1 = buf0 + it.psz;
-    T *scoef = reinterpret_cast<T *>(buf1 + it.psz);
-    const T *coef = (const T *)a.coef;
-    const int nc = W * (a.deg + 1);
-    for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
-
-    T w1[W], w2[W], d1[W], d2[W];
-    T f0 = 0;
-    int zc = 0, yo = 0, xo = 0;
-    if (it.active) {
-        const double *xp = a.xs + 3 * it.p;
-        T f1, f2;
-        zc = cell_frac<T>(xp[0], a.n0, f0);
-        const int yc = cell_frac<T>(xp[1], a.n1, f1);
-        const int xc = cell_frac<T>(xp[2], a.n2, f2);
-        yo = yc - it.y0;
-        xo = xc - it.x0;
-        window_weights_d<T, W>(f1, coef, a.deg, w1, d1);
-        window_weights_d<T, W>(f2, coef, a.deg, w2, d2);
-    }
-    const int zlo = zc - m + 1 - it.zbeg;
-    constexpr int NF = ps_nf<W>();
-    int off[NF], lidx[NF];
-    ps_offsets<NF>(a, it, m, off, lidx);
-    const c_t<T> *grid = (const c_t<T> *)a.grid;
-    const int64_t plane = (int64_t)a.n1 * a.n2;
-    vec2_t<T> stage[NF];
-    ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg, a.n0) * plane, stage);
-    ps_store<T, NF>(buf0, it, lidx, stage);
-    __syncthreads();
-
-    // D0 = sum d0 w1 w2 g, D1 = sum w0 d1 w2 g, D2 = sum w0 w1 d2 g
-    T D0r = 0, D0i = 0, D1r = 0, D1i = 0, D2r = 0, D2i = 0;
-    for (int i = 0; i < it.nplanes; ++i) {
-        const bool more = i + 1 < it.nplanes;
-        if (more) ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg + i + 1, a.n0) * plane, stage);
-        const c_t<T> *pl = (i & 1) ? buf1 : buf0;
-        const int r0 = i - zlo;
-        if (it.active && r0 >= 0 && r0 < W) {
-            T dw0;
-            const T w0 = piece_d<T>(scoef + r0 * (a.deg + 1), a.deg, f0, dw0);
-            T vr = 0, vi = 0, ur = 0, ui = 0, tr = 0, ti = 0;
-            const c_t<T> *base = pl + yo * it.PX + xo;
-            for (int r1 = 0; r1 < W; ++r1) {
-                const c_t<T> *row = base + r1 * it.PX;
-                T sr = 0, si = 0, qr = 0, qi = 0;
-#pragma unroll
-                for (int r2 = 0; r2 < W; ++r2) {
-                    const c_t<T> g = row[r2];
-                    sr += w2[r2] * g.x;
-                    si += w2[r2] * g.y;
-                    qr += d2[r2] * g.x;
-                    qi += d2[r2] * g.y;
-                }
-                vr += w1[r1] * sr; vi += w1[r1] * si;
-                ur += d1[r1] * sr; ui += d1[r1] * si;
-                tr += w1[r1] * qr; ti += w1[r1] * qi;
-            }
-            D0r += dw0 * vr; D0i += dw0 * vi;
-            D1r += w0 * ur;  D1i += w0 * ui;
-            D2r += w0 * tr;  D2i += w0 * ti;
-        }
-        if (more) ps_store<T, NF>((i & 1) ? buf0 : buf1, it, lidx, stage);
         __syncthreads();
-    }
-    if (it.active) {
-        const int pj = a.perm[it.p];
-        const c_t<T> g = ((const c_t<T> *)a.vals)[pj];
-        double *gx = (double *)a.out + 3 * (int64_t)pj;
-        // Re(conj(G) D) = G.x D.x + G.y D.y, times n_d (dt/dx)
-        gx[0] = (double)a.n0 * ((double)g.x * (double)D0r + (double)g.y * (double)D0i);
-        gx[1] = (double)a.n1 * ((double)g.x * (double)D1r + (double)g.y * (double)D1i);
-        gx[2] = (double)a.n2 * ((double)g.x * (double)D2r + (double)g.y * (double)D2i);
-    }
+        interp_range<T, W, 1, true>(a, idx, make_int4(item.x, lo, min(item.z, lo + kPsThreads), 0), smem_raw);
     }
 }
 
@@ -276,11 +203,12 @@ static int spread_w(nfft3_plan_impl *p, const void *f, void *grid) {
 template <typename T, int W>
 static int grad_w(nfft3_plan_impl *p, const void *grid, const void *G, double *gx) {
     if (p->M == 0 || p->sub.count == 0) return NFFT3_OK;
-    PSArgs a = ps_args(p);
+    PSArgs a = interp_args(p);
+    if (!interp_layout_ok(p, a)) return NFFT3_ERR_INVALID_ARG;
     a.grid = grid;
     a.vals = G;
     a.out = gx;
-    const size_t lds = ps_lds(p, 2);
+    const size_t lds = interp_lds(p, a);
     allow_lds((const void *)grad_ps_kernel<T, W>, lds);
     hipLaunchKernelGGL((grad_ps_kernel<T, W>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds, p->stream, a);
     NFFT3_LAUNCH_CHECK("grad_ps_kernel");

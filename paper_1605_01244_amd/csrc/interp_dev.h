@@ -298,8 +298,15 @@ __device__ __forceinline__ bool interp_walk_down(int item, int nplanes, int W) {
 
 // Point slot k of thread t is sorted index item.y + k*256 + t: each slot's
 // wavefronts hold z-adjacent points, so they are active on the same planes.
-template <typename T, int W, int PPT>
-__device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, unsigned char *smem_raw) {
+// GRAD: instead of the values, the derivative sums of the point gradient
+// (grad_x[j, d] = n_d Re(conj(G_j) D_d) with D_0 = sum w0' w1 w2 g,
+// D_1 = sum w0 w1' w2 g, D_2 = sum w0 w1 w2' g): the y derivative weights
+// rotate with the y weights and the x derivative weights are shifted like
+// the x weights, so the reads are the same.
+
+template <typename T, int W, int PPT, bool GRAD>
+__device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, const int4 item,
+                                             unsigned char *smem_raw) {
     constexpr int m = W / 2;
     using U = typename LdsUnit<T>::type;
     constexpr int EPU = LdsUnit<T>::EPU;
@@ -307,7 +314,6 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
     constexpr int NW = NR * EPU;                   // column weights per row
     constexpr int D = 16 / cgcd(W, 16);            // cosets of bank groups
     constexpr int NT = 16 / D;                     // distinct rotations
-    const int4 item = a.items[item_index];
     const PSItem it = ps_range(a, m, item.x, item.y, item.z);
     const int RU = it.PXp / EPU;
     const int bufsz = it.PY * it.PXp;
@@ -328,8 +334,11 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
     const int lane = threadIdx.x & 63;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint64_t gmask = 0xFFFFull << (16 * (lane >> 4));
+    constexpr int WG = GRAD ? W : 1, NWG = GRAD ? NW : 1;
     T w1[PPT][W], wt[PPT][NW];
+    T d1[PPT][WG], dt[PPT][NWG];                   // GRAD: derivative weights
     T f0[PPT], ar[PPT], ai[PPT];
+    T g1r[PPT], g1i[PPT], g2r[PPT], g2i[PPT];      // GRAD: D_1, D_2 (ar, ai hold D_0)
     int zlo[PPT], ub0[PPT], ub1[PPT], tt[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -337,12 +346,15 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
         const bool active = pk < item.z;
         ar[k] = 0;
         ai[k] = 0;
+        g1r[k] = g1i[k] = g2r[k] = g2i[k] = 0;
         zlo[k] = -4 * W;     // never active
         f0[k] = 0;
         int s = 0;           // stencil's first element in the plane
-        T w2[W];
+        T w2[W], e2[WG];
 #pragma unroll
         for (int r = 0; r < W; ++r) { w1[k][r] = 0; w2[r] = 0; }
+#pragma unroll
+        for (int r = 0; r < WG; ++r) { d1[k][r] = 0; e2[r] = 0; }
         if (active) {
             const double *xp = a.xs + 3 * pk;
             T f1, f2;
@@ -351,8 +363,13 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
             const int xc = cell_frac<T>(xp[2], a.n2, f2);
             s = (yc - it.y0) * it.PXp + (xc - it.x0);
             zlo[k] = zc - m + 1 - it.zbeg;      // first plane index of the stencil
-            window_weights<T, W>(f1, coef, a.deg, w1[k]);
-            window_weights<T, W>(f2, coef, a.deg, w2);
+            if constexpr (GRAD) {
+                window_weights_d<T, W>(f1, coef, a.deg, w1[k], d1[k]);
+                window_weights_d<T, W>(f2, coef, a.deg, w2, e2);
+            } else {
+                window_weights<T, W>(f1, coef, a.deg, w1[k]);
+                window_weights<T, W>(f2, coef, a.deg, w2);
+            }
         }
         int u = s / EPU;
         if constexpr (EPU == 2 && D == 2) {
@@ -376,6 +393,15 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
                 v = sh == 0 ? v : (sh == 1 ? v1 : v2);
             }
             wt[k][c] = v;
+            if constexpr (GRAD) {
+                T q = (c < W) ? e2[c] : (T)0;
+                if (EPU == 2) {
+                    const T q1 = (c >= 1 && c - 1 < W) ? e2[c - 1] : (T)0;
+                    const T q2 = (c >= 2 && c - 2 < W) ? e2[c - 2] : (T)0;
+                    q = sh == 0 ? q : (sh == 1 ? q1 : q2);
+                }
+                dt[k][c] = q;
+            }
         }
         // rank within the lane's coset and 16-lane group -> target bank group
         const int cs = u & (D - 1);
@@ -389,6 +415,7 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
         const int delta = (target - u) & 15;   // a multiple of D
         const int t = ((delta / D) * a.qinv) & (NT - 1);
         rotate_rows<T, W, NT>(w1[k], t);
+        if constexpr (GRAD) rotate_rows<T, W, NT>(d1[k], t);
         tt[k] = t;
         ub0[k] = u + t * RU;
         ub1[k] = ub0[k] - W * RU;
@@ -433,8 +460,11 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
         for (int k = 0; k < PPT; ++k) {
             const int r0 = i - zlo[k];
             if (r0 >= 0 && r0 < W) {
-                const T w0 = piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
+                T dw0 = 0;
+                const T w0 = GRAD ? piece_d<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k], dw0)
+                                  : piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
                 T sr = 0, si = 0;
+                T ur = 0, ui = 0, vr2 = 0, vi2 = 0;      // GRAD: sum d1 c, sum w1 q
                 // Reads are software-pipelined in chunks of CH units of a
                 // row: chunk q + LA is issued before chunk q is consumed, and
                 // the scheduling barriers keep that order.  At most
@@ -442,7 +472,8 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
                 // counter can wait on selectively.
                 constexpr int CH = row_chunk(NR);
                 constexpr int S = NR / CH;             // chunks per row
-                constexpr int LA = interp_lookahead<T>(CH);
+                // (the derivative mode holds twice the weights: one chunk ahead)
+                constexpr int LA = GRAD ? (interp_lookahead<T>(CH) > 0 ? 1 : 0) : interp_lookahead<T>(CH);
                 constexpr int NQ = W * S;
                 U g[LA + 1][CH];
 #pragma unroll
@@ -452,7 +483,7 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
 #pragma unroll
                     for (int c = 0; c < CH; ++c) g[q][c] = row[c];
                 }
-                T cr = 0, ci = 0;
+                T cr = 0, ci = 0, qr = 0, qi = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (q + LA < NQ) {
@@ -469,23 +500,50 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
                         if constexpr (EPU == 1) {
                             cr += wt[k][cc] * v.x;
                             ci += wt[k][cc] * v.y;
+                            if constexpr (GRAD) {
+                                qr += dt[k][cc] * v.x;
+                                qi += dt[k][cc] * v.y;
+                            }
                         } else {
                             cr += wt[k][2 * cc] * v.x;
                             ci += wt[k][2 * cc] * v.y;
                             cr += wt[k][2 * cc + 1] * v.z;
                             ci += wt[k][2 * cc + 1] * v.w;
+                            if constexpr (GRAD) {
+                                qr += dt[k][2 * cc] * v.x;
+                                qi += dt[k][2 * cc] * v.y;
+                                qr += dt[k][2 * cc + 1] * v.z;
+                                qi += dt[k][2 * cc + 1] * v.w;
+                            }
                         }
                     }
                     if (q % S == S - 1) {
                         sr += w1[k][q / S] * cr;
                         si += w1[k][q / S] * ci;
+                        if constexpr (GRAD) {
+                            ur += d1[k][q / S] * cr;
+                            ui += d1[k][q / S] * ci;
+                            vr2 += w1[k][q / S] * qr;
+                            vi2 += w1[k][q / S] * qi;
+                            qr = 0;
+                            qi = 0;
+                        }
                         cr = 0;
                         ci = 0;
                     }
                     if constexpr (LA > 0) __builtin_amdgcn_sched_barrier(0);
                 }
-                ar[k] += w0 * sr;
-                ai[k] += w0 * si;
+                if constexpr (GRAD) {
+                    ar[k] += dw0 * sr;    // D_0
+                    ai[k] += dw0 * si;
+                    g1r[k] += w0 * ur;    // D_1
+                    g1i[k] += w0 * ui;
+                    g2r[k] += w0 * vr2;   // D_2
+                    g2i[k] += w0 * vi2;
+                } else {
+                    ar[k] += w0 * sr;
+                    ai[k] += w0 * si;
+                }
             }
         }
         if constexpr (kDirect) {
@@ -498,10 +556,26 @@ __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, uns
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int pk = item.y + k * kPsThreads + threadIdx.x;
-        if (pk < item.z) ((c_t<T> *)a.out)[a.perm[pk]] = cmk<T>(ar[k], ai[k]);
+        if (pk >= item.z) continue;
+        const int pj = a.perm[pk];
+        if constexpr (GRAD) {
+            // Re(conj(G) D) = G.x D.x + G.y D.y, times n_d (dt/dx)
+            const c_t<T> g = ((const c_t<T> *)a.vals)[pj];
+            double *gx = (double *)a.out + 3 * (int64_t)pj;
+            gx[0] = (double)a.n0 * ((double)g.x * (double)ar[k] + (double)g.y * (double)ai[k]);
+            gx[1] = (double)a.n1 * ((double)g.x * (double)g1r[k] + (double)g.y * (double)g1i[k]);
+            gx[2] = (double)a.n2 * ((double)g.x * (double)g2r[k] + (double)g.y * (double)g2i[k]);
+        } else {
+            ((c_t<T> *)a.out)[pj] = cmk<T>(ar[k], ai[k]);
+        }
     }
 }
 
+
+template <typename T, int W, int PPT, bool GRAD = false>
+__device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, unsigned char *smem_raw) {
+    interp_range<T, W, PPT, GRAD>(a, item_index, a.items[item_index], smem_raw);
+}
 
 inline PSArgs ps_args(const nfft3_plan_impl *p) {
     PSArgs a;
