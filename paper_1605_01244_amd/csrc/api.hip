@@ -131,17 +131,10 @@ int window_poly(int m, double b, double tol, int cap_deg, std::vector<double> &c
 // Radices 8, 4, 2, 3, 5 whose product is n (largest first).
 bool factor_radices(int n, std::vector<int> &rad) {
     rad.clear();
-    int a = 0;
-    while (n % 2 == 0) { n /= 2; ++a; }
-    int q = a / 3, r = a % 3;
-    if (r == 1 && q > 0) { q -= 1; r = 4; }
-    for (int i = 0; i < q; ++i) rad.push_back(8);
-    if (r == 4) { rad.push_back(4); rad.push_back(4); }
-    else if (r == 2) rad.push_back(4);
-    else if (r == 1) rad.push_back(2);
-    while (n % 3 == 0) { n /= 3; rad.push_back(3); }
-    while (n % 5 == 0) { n /= 5; rad.push_back(5); }
-    return n == 1 && rad.size() <= 16;
+    const int nr = st_nrad(n);
+    if (nr < 1 || nr > 16) return false;
+    for (int s = 0; s < nr; ++s) rad.push_back(st_radix(n, s));
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -204,11 +197,11 @@ template <typename T>
 static int upload_stage_twiddles(int n, void **dst) {
     // per-stage tables of the compile-time power-of-two engine
     const long double pi = 3.14159265358979323846264338327950288L;
-    const int size = p2_tw_size(n);
+    const int size = st_tw_size(n);
     if (size == 0) return NFFT3_OK;
     std::vector<T> h(2 * (size_t)size, (T)0);
-    for (int s = 1; s < p2_nrad(n); ++s) {
-        const int ns = p2_ns(n, s), R = p2_radix(n, s), off = p2_tw_offset(n, s);
+    for (int s = 1; s < st_nrad(n); ++s) {
+        const int ns = st_ns(n, s), R = st_radix(n, s), off = st_tw_offset(n, s);
         for (int k = 0; k < ns; ++k)
             for (int r = 0; r < R; ++r) {
                 const long long num = (long long)r * k, den = (long long)ns * R;
@@ -297,11 +290,9 @@ static int build_plan(nfft3_plan_impl *p) {
         rc = f64 ? upload_twiddles<double>((int)p->n[d], &p->fft[d].tw)
                  : upload_twiddles<float>((int)p->n[d], &p->fft[d].tw);
         if (rc) return rc;
-        if (is_pow2((int)p->n[d])) {
-            rc = f64 ? upload_stage_twiddles<double>((int)p->n[d], &p->fft[d].stw)
-                     : upload_stage_twiddles<float>((int)p->n[d], &p->fft[d].stw);
-            if (rc) return rc;
-        }
+        rc = f64 ? upload_stage_twiddles<double>((int)p->n[d], &p->fft[d].stw)
+                 : upload_stage_twiddles<float>((int)p->n[d], &p->fft[d].stw);
+        if (rc) return rc;
     }
     std::vector<double> coef;
     const double tol = f64 ? 4e-16 : 2e-8;

@@ -3,14 +3,18 @@
 //
 // Each (plan, field) pair is a transform with four stages: the row pass
 // (deconvolve + zero-pad + FFT along axis 2), the column passes along axes 1
-// and 0, and the window sums.  The batch runs as four launches, one per
-// stage, each covering the work items (row blocks, column tiles, point items)
-// of EVERY transform: workgroup b finds its transform t by a binary search in
-// the per-stage prefix table of item counts and runs item b - first[t] with
-// t's arguments.  Kernel boundaries order the stages, so no workgroup ever
-// waits on another.  The stage bodies are the ones of the single-plan kernels
-// (same launch shapes), so a batched result equals the sequential one bit for
-// bit.
+// and 0, and the window sums.  Each FFT stage runs as one launch per distinct
+// transform length along its axis (a kernel specialised for that length, or
+// one generic launch for lengths the compile-time engine does not cover),
+// the window sums as one launch; each launch covers the work items (row
+// blocks, column tiles, point items) of every transform in its group:
+// workgroup b finds its transform by a binary search in the group's prefix
+// table of item counts and runs item b - first[t] with that transform's
+// arguments.  Kernel boundaries order the stages, so no workgroup ever waits
+// on another.  The stage bodies and launch shapes are the ones of the
+// single-plan kernels, so a batched result equals the sequential one bit for
+// bit.  (A single kernel over all lengths holds every specialisation's code
+// and ran several times slower.)
 #include <algorithm>
 #include <vector>
 
@@ -42,35 +46,79 @@ __device__ __forceinline__ int batch_find(const int *__restrict__ first, int X, 
     return lo;
 }
 
-template <typename T>
+// group g of a stage: transforms ids[0 .. X), prefix table first[0 .. X]
+template <typename T, int L>
 __global__ void __launch_bounds__(kBRowThreads)
-batch_rows_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ first, int X) {
+batch_rows_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids, const int *__restrict__ first,
+                  int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int t = batch_find(first, X, blockIdx.x);
-    rows_any<T, 0, kBRowThreads>(xf[t].rows, blockIdx.x - first[t], smem_raw);
+    const int g = batch_find(first, X, blockIdx.x);
+    const BatchXform &b = xf[ids[g]];
+    if constexpr (L == 0) rows_body<T, 0, kBRowThreads>(b.rows, blockIdx.x - first[g], smem_raw);
+    else rows_body_s<T, 0, kBRowThreads, L, static_rows_nl<T>(L)>(b.rows, blockIdx.x - first[g], smem_raw);
 }
 
-template <typename T, int AXIS>
+template <typename T, int AXIS, int L>
 __global__ void __launch_bounds__(kBColThreads)
-batch_cols_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ first, int X) {
+batch_cols_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids, const int *__restrict__ first,
+                  int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int t = batch_find(first, X, blockIdx.x);
-    const int tile = blockIdx.x - first[t];
-    if (AXIS == 1) {
-        const int gx = xf[t].gx1;
-        cols_any<T, true, kBColThreads, 16>(xf[t].c1, tile % gx, tile / gx, smem_raw);
-    } else {
-        const int gx = xf[t].gx0;
-        cols_any<T, true, kBColThreads, 16>(xf[t].c0, tile % gx, tile / gx, smem_raw);
-    }
+    const int g = batch_find(first, X, blockIdx.x);
+    const BatchXform &b = xf[ids[g]];
+    const int tile = blockIdx.x - first[g];
+    const ColArgs &c = AXIS == 1 ? b.c1 : b.c0;
+    const int gx = AXIS == 1 ? b.gx1 : b.gx0;
+    if constexpr (L == 0) cols_body<T, true, kBColThreads, 16>(c, tile % gx, tile / gx, smem_raw);
+    else cols_body_s<T, true, kBColThreads, L, static_cols_nl<T>(L)>(c, tile % gx, tile / gx, smem_raw);
 }
 
 template <typename T, int W, int PPT>
 __global__ void __launch_bounds__(kPsThreads)
-batch_interp_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ first, int X) {
+batch_interp_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids, const int *__restrict__ first,
+                    int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int t = batch_find(first, X, blockIdx.x);
-    interp_body<T, W, PPT>(xf[t].ip, blockIdx.x - first[t], smem_raw);
+    const int g = batch_find(first, X, blockIdx.x);
+    interp_body<T, W, PPT>(xf[ids[g]].ip, blockIdx.x - first[g], smem_raw);
+}
+
+// one launch of a stage over one group of transforms
+struct BatchGroup {
+    int stage;        // 0 rows, 1 cols axis 1, 2 cols axis 0, 3 window sums
+    int len;          // static length, or 0 for the generic kernels
+    std::vector<int> ids;
+    size_t lds = 0;
+    int total = 0;
+    size_t off_ids = 0, off_first = 0;
+};
+
+template <typename T, int L>
+static void launch_group_static(const BatchGroup &g, const BatchXform *dxf, const int *dids, const int *dfirst,
+                                hipStream_t s) {
+    const int X = (int)g.ids.size();
+    if (g.stage == 0) {
+        hipLaunchKernelGGL((batch_rows_kernel<T, L>), dim3((unsigned)g.total), dim3(kBRowThreads), g.lds, s, dxf,
+                           dids, dfirst, X);
+    } else if (g.stage == 1) {
+        allow_lds((const void *)batch_cols_kernel<T, 1, L>, g.lds);
+        hipLaunchKernelGGL((batch_cols_kernel<T, 1, L>), dim3((unsigned)g.total), dim3(kBColThreads), g.lds, s,
+                           dxf, dids, dfirst, X);
+    } else {
+        allow_lds((const void *)batch_cols_kernel<T, 0, L>, g.lds);
+        hipLaunchKernelGGL((batch_cols_kernel<T, 0, L>), dim3((unsigned)g.total), dim3(kBColThreads), g.lds, s,
+                           dxf, dids, dfirst, X);
+    }
+}
+
+template <typename T>
+static void launch_group_fft(const BatchGroup &g, const BatchXform *dxf, const int *dids, const int *dfirst,
+                             hipStream_t s) {
+    switch (g.len) {
+#define NFFT3_BATCH_LEN(L) \
+        case L: launch_group_static<T, L>(g, dxf, dids, dfirst, s); return;
+        NFFT3_STATIC_LENGTHS(NFFT3_BATCH_LEN)
+#undef NFFT3_BATCH_LEN
+        default: launch_group_static<T, 0>(g, dxf, dids, dfirst, s); return;
+    }
 }
 
 // device-side descriptors of the batched launcher (grown as needed, kept)
@@ -85,7 +133,7 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
     const int F = (int)fields.size();
     const int X = T_ * F;
     std::vector<BatchXform> xf((size_t)X);
-    size_t lds[kStages] = {0, 0, 0, 0};
+    size_t lds_ip = 0;
     hipStream_t stream = plans[0]->stream;
     for (int t = 0; t < T_; ++t) {
         nfft3_plan_impl *p = plans[t];
@@ -110,26 +158,60 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             b.ntile[1] = b.gx1 * (int)p->N[0];
             b.ntile[2] = b.gx0 * (int)p->n[1];
             b.ntile[3] = (p->M > 0) ? (int)p->sub.count : 0;
-            lds[0] = std::max(lds[0], row_lds<T>(b.rows));
-            lds[1] = std::max(lds[1], col_lds<T>(b.c1));
-            lds[2] = std::max(lds[2], col_lds<T>(b.c0));
-            lds[3] = std::max(lds[3], interp_lds(p, b.ip));
+            lds_ip = std::max(lds_ip, interp_lds(p, b.ip));
         }
     }
-    // per-stage prefix tables of item counts: first[s][t], X + 1 entries each
-    std::vector<int> first((size_t)kStages * (X + 1));
-    int total[kStages];
-    for (int s = 0; s < kStages; ++s) {
+    // groups: per FFT stage one per distinct axis length (static lengths
+    // only when the pass uses the compile-time engine's line counts), one for
+    // the window sums
+    std::vector<BatchGroup> groups;
+    auto group_of = [&](int stage, int len) -> BatchGroup & {
+        for (BatchGroup &g : groups)
+            if (g.stage == stage && g.len == len) return g;
+        groups.push_back(BatchGroup());
+        groups.back().stage = stage;
+        groups.back().len = len;
+        return groups.back();
+    };
+    for (int t = 0; t < X; ++t) {
+        const BatchXform &b = xf[t];
+        if (b.ntile[0] > 0) {
+            const int L = b.rows.n;
+            const bool st = static_fft_len(L) && b.rows.lpw == static_rows_nl<T>(L);
+            BatchGroup &g = group_of(0, st ? L : 0);
+            g.ids.push_back(t);
+            g.lds = std::max(g.lds, row_lds<T>(b.rows));
+        }
+        for (int ax = 1; ax <= 2; ++ax) {
+            const ColArgs &c = ax == 1 ? b.c1 : b.c0;
+            if (b.ntile[ax] <= 0) continue;
+            const bool st = static_fft_len(c.n) && c.C == static_cols_nl<T>(c.n);
+            BatchGroup &g = group_of(ax, st ? c.n : 0);
+            g.ids.push_back(t);
+            g.lds = std::max(g.lds, col_lds<T>(c));
+        }
+        if (b.ntile[3] > 0) {
+            BatchGroup &g = group_of(3, 0);
+            g.ids.push_back(t);
+        }
+    }
+    // device layout: descriptors, then per group its ids and prefix table
+    std::vector<int> ints;
+    size_t off = ((sizeof(BatchXform) * X + 255) / 256) * 256;
+    for (BatchGroup &g : groups) {
+        g.off_ids = off + sizeof(int) * ints.size();
+        for (int t : g.ids) ints.push_back(t);
+        g.off_first = off + sizeof(int) * ints.size();
         int acc = 0;
-        for (int t = 0; t < X; ++t) {
-            first[(size_t)s * (X + 1) + t] = acc;
-            acc += xf[t].ntile[s];
+        for (int t : g.ids) {
+            ints.push_back(acc);
+            acc += xf[t].ntile[g.stage];
         }
-        first[(size_t)s * (X + 1) + X] = acc;
-        total[s] = acc;
+        ints.push_back(acc);
+        g.total = acc;
+        if (g.stage == 3) g.lds = lds_ip;
     }
-    const size_t off_first = ((sizeof(BatchXform) * X + 255) / 256) * 256;
-    const size_t need = off_first + sizeof(int) * first.size();
+    const size_t need = off + sizeof(int) * ints.size();
     if (need > g_batch_cap) {
         if (g_batch_buf) {
             NFFT3_HIP_TRY(hipStreamSynchronize(stream));
@@ -142,32 +224,23 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
     }
     char *base = (char *)g_batch_buf;
     NFFT3_HIP_TRY(hipMemcpyAsync(base, xf.data(), sizeof(BatchXform) * X, hipMemcpyHostToDevice, stream));
-    NFFT3_HIP_TRY(hipMemcpyAsync(base + off_first, first.data(), sizeof(int) * first.size(),
-                                 hipMemcpyHostToDevice, stream));
+    NFFT3_HIP_TRY(hipMemcpyAsync(base + off, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, stream));
     const BatchXform *dxf = (const BatchXform *)base;
-    const int *dfirst = (const int *)(base + off_first);
-    if (total[0] > 0) {
-        hipLaunchKernelGGL(batch_rows_kernel<T>, dim3((unsigned)total[0]), dim3(kBRowThreads), lds[0], stream, dxf,
-                           dfirst, X);
-        NFFT3_LAUNCH_CHECK("batch_rows_kernel");
-    }
-    if (total[1] > 0) {
-        allow_lds((const void *)batch_cols_kernel<T, 1>, lds[1]);
-        hipLaunchKernelGGL((batch_cols_kernel<T, 1>), dim3((unsigned)total[1]), dim3(kBColThreads), lds[1], stream,
-                           dxf, dfirst + (X + 1), X);
-        NFFT3_LAUNCH_CHECK("batch_cols_kernel");
-    }
-    if (total[2] > 0) {
-        allow_lds((const void *)batch_cols_kernel<T, 0>, lds[2]);
-        hipLaunchKernelGGL((batch_cols_kernel<T, 0>), dim3((unsigned)total[2]), dim3(kBColThreads), lds[2], stream,
-                           dxf, dfirst + 2 * (X + 1), X);
-        NFFT3_LAUNCH_CHECK("batch_cols_kernel");
-    }
-    if (total[3] > 0) {
-        allow_lds((const void *)batch_interp_kernel<T, W, PPT>, lds[3]);
-        hipLaunchKernelGGL((batch_interp_kernel<T, W, PPT>), dim3((unsigned)total[3]), dim3(kPsThreads), lds[3],
-                           stream, dxf, dfirst + 3 * (X + 1), X);
-        NFFT3_LAUNCH_CHECK("batch_interp_kernel");
+    for (int stage = 0; stage < kStages; ++stage) {
+        for (const BatchGroup &g : groups) {
+            if (g.stage != stage || g.total == 0) continue;
+            const int *dids = (const int *)(base + g.off_ids);
+            const int *dfirst = (const int *)(base + g.off_first);
+            if (stage < 3) {
+                launch_group_fft<T>(g, dxf, dids, dfirst, stream);
+                NFFT3_LAUNCH_CHECK("batch_fft_kernel");
+            } else {
+                allow_lds((const void *)batch_interp_kernel<T, W, PPT>, g.lds);
+                hipLaunchKernelGGL((batch_interp_kernel<T, W, PPT>), dim3((unsigned)g.total), dim3(kPsThreads),
+                                   g.lds, stream, dxf, dids, dfirst, (int)g.ids.size());
+                NFFT3_LAUNCH_CHECK("batch_interp_kernel");
+            }
+        }
     }
     // the host descriptors above are copied from pageable memory; make sure
     // the copies are done before the vectors go away

@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kColThreads) fft_cols_kernel(ColArgs a) {
     cols_body<T, FWD, kColThreads, 16>(a, blockIdx.x, blockIdx.y, smem_raw);
 }
 
-// compile-time-engine passes (power-of-two n of static_fft_len)
+// compile-time-engine passes (the lengths of static_fft_len)
 template <typename T, int MODE, int N>
 __global__ void __launch_bounds__(kRowThreads) fft_rows_kernel_s(RowArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kRowThreads) fft_rows_kernel_s(RowArgs a) {
 template <typename T, bool FWD, int N>
 __global__ void __launch_bounds__(kColThreads) fft_cols_kernel_s(ColArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cols_body_s<T, FWD, kColThreads, N, static_cols_nl<T>()>(a, blockIdx.x, blockIdx.y, smem_raw);
+    cols_body_s<T, FWD, kColThreads, N, static_cols_nl<T>(N)>(a, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 template <typename T, int MODE, int N>
@@ -61,24 +61,24 @@ template <typename T, int MODE>
 static bool rows_static(const RowArgs &a, dim3 g, size_t lds, hipStream_t s) {
     if (!static_fft_len(a.n) || a.lpw != static_rows_nl<T>(a.n)) return false;
     switch (a.n) {
-        case 64: launch_rows_s<T, MODE, 64>(g, lds, s, a); break;
-        case 128: launch_rows_s<T, MODE, 128>(g, lds, s, a); break;
-        case 256: launch_rows_s<T, MODE, 256>(g, lds, s, a); break;
-        default: launch_rows_s<T, MODE, 512>(g, lds, s, a); break;
+#define NFFT3_ROWS_LAUNCH(L) \
+        case L: launch_rows_s<T, MODE, L>(g, lds, s, a); return true;
+        NFFT3_STATIC_LENGTHS(NFFT3_ROWS_LAUNCH)
+#undef NFFT3_ROWS_LAUNCH
+        default: return false;
     }
-    return true;
 }
 
 template <typename T, bool FWD>
 static bool cols_static(const ColArgs &a, dim3 g, size_t lds, hipStream_t s) {
-    if (!static_fft_len(a.n) || a.C != static_cols_nl<T>()) return false;
+    if (!static_fft_len(a.n) || a.C != static_cols_nl<T>(a.n)) return false;
     switch (a.n) {
-        case 64: launch_cols_s<T, FWD, 64>(g, lds, s, a); break;
-        case 128: launch_cols_s<T, FWD, 128>(g, lds, s, a); break;
-        case 256: launch_cols_s<T, FWD, 256>(g, lds, s, a); break;
-        default: launch_cols_s<T, FWD, 512>(g, lds, s, a); break;
+#define NFFT3_COLS_LAUNCH(L) \
+        case L: launch_cols_s<T, FWD, L>(g, lds, s, a); return true;
+        NFFT3_STATIC_LENGTHS(NFFT3_COLS_LAUNCH)
+#undef NFFT3_COLS_LAUNCH
+        default: return false;
     }
-    return true;
 }
 
 template <typename T>

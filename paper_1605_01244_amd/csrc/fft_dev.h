@@ -211,7 +211,7 @@ __device__ __forceinline__ void fft_lines(c_t<T> *buf, int ls, int nlines, int n
 // from its own table (8 entries per k, so one butterfly's are contiguous).
 template <typename T, int N, int S, int NL, int LS, int NT, bool FWD, bool LINE_FAST, class LD, class ST>
 __device__ __forceinline__ void sfft_stage(c_t<T> *buf, const c_t<T> *__restrict__ stw, LD &ld, ST &st) {
-    constexpr int R = p2_radix(N, S), NS = p2_ns(N, S), NRAD = p2_nrad(N);
+    constexpr int R = st_radix(N, S), NS = st_ns(N, S), NRAD = st_nrad(N);
     constexpr bool FIRST = S == 0, LAST = S == NRAD - 1;
     constexpr int NBL = N / R, NB = NL * NBL, BPT = (NB + NT - 1) / NT;
     const int tid = threadIdx.x;
@@ -239,9 +239,9 @@ __device__ __forceinline__ void sfft_stage(c_t<T> *buf, const c_t<T> *__restrict
         if (NB % NT == 0 || bt < NB) {
             const int j = LINE_FAST ? bt / NL : bt % NBL;
             const int line = LINE_FAST ? bt % NL : bt / NBL;
-            const int k = j & (NS - 1);
+            const int k = j % NS;
             if constexpr (!FIRST) {
-                const c_t<T> *w = stw + p2_tw_offset(N, S) + k * 8;
+                const c_t<T> *w = stw + st_tw_offset(N, S) + k * 8;
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[i][r] = FWD ? cmul(v[i][r], w[r]) : cmulc(v[i][r], w[r]);
             }
@@ -262,19 +262,42 @@ __device__ __forceinline__ void sfft_stage(c_t<T> *buf, const c_t<T> *__restrict
 template <typename T, int N, int S, int NL, int LS, int NT, bool FWD, bool LINE_FAST, class LD, class ST>
 __device__ __forceinline__ void sfft_lines(c_t<T> *buf, const c_t<T> *__restrict__ stw, LD &ld, ST &st) {
     sfft_stage<T, N, S, NL, LS, NT, FWD, LINE_FAST>(buf, stw, ld, st);
-    if constexpr (S + 1 < p2_nrad(N)) sfft_lines<T, N, S + 1, NL, LS, NT, FWD, LINE_FAST>(buf, stw, ld, st);
+    if constexpr (S + 1 < st_nrad(N)) sfft_lines<T, N, S + 1, NL, LS, NT, FWD, LINE_FAST>(buf, stw, ld, st);
 }
 
-// Power-of-two lengths served by the compile-time engine, and its lines per
-// workgroup: rows fill 32 KiB of LDS (as make_row_args), column tiles are
-// 128-byte segments (as make_col_args).
-constexpr bool static_fft_len(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
-template <typename T>
-constexpr int static_rows_nl(int n) {
-    return 32768 / (n * (int)sizeof(c_t<T>)) < 64 ? 32768 / (n * (int)sizeof(c_t<T>)) : 64;
+// Lengths served by the compile-time engine, and its lines per workgroup,
+// computed exactly as the host does (make_row_args / make_col_args with
+// lines_fit over the same radix plan), so both sides agree.
+constexpr bool static_fft_len(int n) {
+    return n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512;
+}
+constexpr int st_lines_fit(int n, int vmax, int cap, int nthreads) {
+    int best = 1;
+    for (int L = 1; L <= cap; ++L) {
+        bool ok = true;
+        for (int s = 0; s < st_nrad(n); ++s) {
+            const int R = st_radix(n, s);
+            const int per = (L * (n / R) + nthreads - 1) / nthreads;
+            if (per > vmax / R) { ok = false; break; }
+        }
+        if (!ok) break;
+        best = L;
+    }
+    return best;
 }
 template <typename T>
-constexpr int static_cols_nl() { return 128 / (int)sizeof(c_t<T>); }
+constexpr int static_rows_nl(int n) {
+    int cap = 32768 / (n * (int)sizeof(c_t<T>));
+    cap = cap < 1 ? 1 : (cap > 64 ? 64 : cap);
+    return st_lines_fit(n, 16, cap, 256);
+}
+template <typename T>
+constexpr int static_cols_nl(int n) {
+    int C = 128 / (int)sizeof(c_t<T>);
+    while (C > 1 && C * (n + 1) * (int)sizeof(c_t<T>) > 80 * 1024) C /= 2;
+    const int f = st_lines_fit(n, 16, C, 512);
+    return f < C ? f : C;
+}
 
 // FFT position -> compact index of a pruned line of L entries (frequency
 // k = pos or pos - n; kept when -L/2 <= k < L/2), or -1.
@@ -504,34 +527,9 @@ __device__ __forceinline__ void cols_body_s(const ColArgs &a, int bx, int by, un
     sfft_lines<T, N, 0, NC, N + 1, NT, FWD, true>(buf, (const c_t<T> *)a.stw, ld, st);
 }
 
-// Pass bodies that take the compile-time engine when it serves (n, lines) and
-// the generic one otherwise (a uniform branch per workgroup; used where one
-// kernel covers transforms of several sizes).
-template <typename T, int MODE, int NT>
-__device__ __forceinline__ void rows_any(const RowArgs &a, int blk, unsigned char *smem_raw) {
-    if (static_fft_len(a.n) && a.lpw == static_rows_nl<T>(a.n)) {
-        switch (a.n) {
-            case 64: rows_body_s<T, MODE, NT, 64, static_rows_nl<T>(64)>(a, blk, smem_raw); return;
-            case 128: rows_body_s<T, MODE, NT, 128, static_rows_nl<T>(128)>(a, blk, smem_raw); return;
-            case 256: rows_body_s<T, MODE, NT, 256, static_rows_nl<T>(256)>(a, blk, smem_raw); return;
-            default: rows_body_s<T, MODE, NT, 512, static_rows_nl<T>(512)>(a, blk, smem_raw); return;
-        }
-    }
-    rows_body<T, MODE, NT>(a, blk, smem_raw);
-}
-
-template <typename T, bool FWD, int NT, int VMAX>
-__device__ __forceinline__ void cols_any(const ColArgs &a, int bx, int by, unsigned char *smem_raw) {
-    if (static_fft_len(a.n) && a.C == static_cols_nl<T>()) {
-        switch (a.n) {
-            case 64: cols_body_s<T, FWD, NT, 64, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
-            case 128: cols_body_s<T, FWD, NT, 128, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
-            case 256: cols_body_s<T, FWD, NT, 256, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
-            default: cols_body_s<T, FWD, NT, 512, static_cols_nl<T>()>(a, bx, by, smem_raw); return;
-        }
-    }
-    cols_body<T, FWD, NT, VMAX>(a, bx, by, smem_raw);
-}
+// The lengths the compile-time engine is instantiated for (2^a 3^b 5^c
+// oversampled lengths of the common coefficient sizes).
+#define NFFT3_STATIC_LENGTHS(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 
 // Largest number of lines such that every stage fits VMAX values per thread.
 inline int lines_fit(const FftAxisPlan &f, int vmax, int cap, int nthreads) {

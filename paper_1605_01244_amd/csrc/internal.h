@@ -58,35 +58,53 @@ struct FftAxisPlan {
     int nrad = 0;             // number of radix stages
     int radix[16] = {0};      // radices in application order
     void *tw = nullptr;       // device twiddles exp(-2 pi i k/n), k = 0..n-1 (c_t<T>)
-    void *stw = nullptr;      // power-of-two n: per-stage twiddle tables (p2_tw_offset)
+    void *stw = nullptr;      // per-stage twiddle tables of the compile-time engine (st_tw_offset)
 };
 
-// Compile-time radix plan of a power-of-two length n = 2^l: floor(l/3)
-// radix-8 stages, then one radix-2 or radix-4 stage for l mod 3 = 1 or 2.
-constexpr int p2_log(int n) {
-    int l = 0;
-    while ((1 << l) < n) ++l;
-    return l;
+// Radix plan of a length n = 2^a 3^b 5^c, in application order: radix-8
+// stages, then one radix-4 or radix-2 stage for a mod 3 = 2 or 1 (two
+// radix-4 stages instead of 8 x 2 when a mod 3 = 1 and a >= 4), then the
+// radix-3 and the radix-5 stages.  The host's FFT plans and the compile-time
+// engine both use it.
+constexpr int st_nrad(int n) {
+    int a = 0;
+    while (n % 2 == 0) { n /= 2; ++a; }
+    int q = a / 3, r = a % 3, c = 0;
+    if (r == 1 && q > 0) { q -= 1; r = 4; }
+    c = q + (r == 4 ? 2 : (r ? 1 : 0));
+    while (n % 3 == 0) { n /= 3; ++c; }
+    while (n % 5 == 0) { n /= 5; ++c; }
+    return n == 1 ? c : -1;
 }
-constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
-constexpr int p2_nrad(int n) { return p2_log(n) / 3 + (p2_log(n) % 3 ? 1 : 0); }
-constexpr int p2_radix(int n, int s) {
-    return s < p2_log(n) / 3 ? 8 : (p2_log(n) % 3 == 1 ? 2 : 4);
+constexpr int st_radix(int n, int s) {
+    int a = 0;
+    while (n % 2 == 0) { n /= 2; ++a; }
+    int q = a / 3, r = a % 3;
+    if (r == 1 && q > 0) { q -= 1; r = 4; }
+    if (s < q) return 8;
+    s -= q;
+    if (r == 4) { if (s < 2) return 4; s -= 2; }
+    else if (r == 2) { if (s < 1) return 4; s -= 1; }
+    else if (r == 1) { if (s < 1) return 2; s -= 1; }
+    int b = 0;
+    while (n % 3 == 0) { n /= 3; ++b; }
+    return s < b ? 3 : 5;
 }
 // product of the radices before stage s (the Stockham span Ns)
-constexpr int p2_ns(int n, int s) {
+constexpr int st_ns(int n, int s) {
     int ns = 1;
-    for (int i = 0; i < s; ++i) ns *= p2_radix(n, i);
+    for (int i = 0; i < s; ++i) ns *= st_radix(n, i);
     return ns;
 }
-// Stage s >= 1 twiddles: entry [k * 8 + r] = exp(-2 pi i r k / (Ns R)),
-// k < Ns, r < R; this is the offset of stage s's table.
-constexpr int p2_tw_offset(int n, int s) {
+// Stage s >= 1 twiddles of the compile-time engine: entry [k * 8 + r] =
+// exp(-2 pi i r k / (Ns R)), k < Ns, r < R; this is the offset of stage s's
+// table.
+constexpr int st_tw_offset(int n, int s) {
     int off = 0;
-    for (int i = 1; i < s; ++i) off += p2_ns(n, i) * 8;
+    for (int i = 1; i < s; ++i) off += st_ns(n, i) * 8;
     return off;
 }
-constexpr int p2_tw_size(int n) { return p2_tw_offset(n, p2_nrad(n)); }
+constexpr int st_tw_size(int n) { return st_nrad(n) > 0 ? st_tw_offset(n, st_nrad(n)) : 0; }
 
 // Points are sorted by (tile, z-cell); a tile is By x Bx cells of the (y, x)
 // plane.  Work items for the window-sum kernels are at most Subproblems::maxpts
