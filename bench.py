@@ -88,7 +88,8 @@ def parse():
 def bench_batched(nf, torch, dev, workloads, stream):
     """64 coefficient sets of N in {64, 96, 128}^3 with lognormal point
     counts, each with its three derivative fields: one nfft3_batch_trafo per
-    form (four launches over all 256 transforms), timed with HIP events."""
+    form (one launch per FFT stage and axis length plus one window-sum launch,
+    each over all 256 transforms), timed with HIP events."""
     t0 = time.time()
     sets = workloads.batched_sets(64)
     log(f"batched inputs generated in {time.time() - t0:.1f}s")
