@@ -25,7 +25,6 @@ namespace nfft3 {
 
 constexpr int kStages = 4;
 constexpr int kBRowThreads = 256;
-constexpr int kBColThreads = 512;
 
 struct BatchXform {
     RowArgs rows;
@@ -59,7 +58,7 @@ batch_rows_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids
 }
 
 template <typename T, int AXIS, int L>
-__global__ void __launch_bounds__(kBColThreads)
+__global__ void __launch_bounds__(L == 0 ? kColsThreadsGeneric : kColsThreads)
 batch_cols_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids, const int *__restrict__ first,
                   int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -68,8 +67,8 @@ batch_cols_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids
     const int tile = blockIdx.x - first[g];
     const ColArgs &c = AXIS == 1 ? b.c1 : b.c0;
     const int gx = AXIS == 1 ? b.gx1 : b.gx0;
-    if constexpr (L == 0) cols_body<T, true, kBColThreads, 16>(c, tile % gx, tile / gx, smem_raw);
-    else cols_body_s<T, true, kBColThreads, L, static_cols_nl<T>(L)>(c, tile % gx, tile / gx, smem_raw);
+    if constexpr (L == 0) cols_body<T, true, kColsThreadsGeneric, 16>(c, tile % gx, tile / gx, smem_raw);
+    else cols_body_s<T, true, kColsThreads, L, static_cols_nl<T>(L)>(c, tile % gx, tile / gx, smem_raw);
 }
 
 template <typename T, int W, int PPT>
@@ -100,11 +99,11 @@ static void launch_group_static(const BatchGroup &g, const BatchXform *dxf, cons
                            dids, dfirst, X);
     } else if (g.stage == 1) {
         allow_lds((const void *)batch_cols_kernel<T, 1, L>, g.lds);
-        hipLaunchKernelGGL((batch_cols_kernel<T, 1, L>), dim3((unsigned)g.total), dim3(kBColThreads), g.lds, s,
+        hipLaunchKernelGGL((batch_cols_kernel<T, 1, L>), dim3((unsigned)g.total), dim3(L == 0 ? kColsThreadsGeneric : kColsThreads), g.lds, s,
                            dxf, dids, dfirst, X);
     } else {
         allow_lds((const void *)batch_cols_kernel<T, 0, L>, g.lds);
-        hipLaunchKernelGGL((batch_cols_kernel<T, 0, L>), dim3((unsigned)g.total), dim3(kBColThreads), g.lds, s,
+        hipLaunchKernelGGL((batch_cols_kernel<T, 0, L>), dim3((unsigned)g.total), dim3(L == 0 ? kColsThreadsGeneric : kColsThreads), g.lds, s,
                            dxf, dids, dfirst, X);
     }
 }
@@ -146,8 +145,8 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             BatchXform &b = xf[(size_t)t * F + f];
             void *grid = f == 0 ? p->grid : p->extra_grids[f - 1];
             b.rows = make_row_args<T>(p, fhat[t], grid, fields[f], kBRowThreads);
-            b.c1 = make_col_args<T>(p, grid, 1, (int)p->N[1], (int)p->n[1], p->n[1] * p->n[2], kBColThreads, 16);
-            b.c0 = make_col_args<T>(p, grid, 0, (int)p->N[0], (int)p->n[0], p->n[2], kBColThreads, 16);
+            b.c1 = make_col_args<T>(p, grid, 1, (int)p->N[1], (int)p->n[1], p->n[1] * p->n[2]);
+            b.c0 = make_col_args<T>(p, grid, 0, (int)p->N[0], (int)p->n[0], p->n[2]);
             b.ip = interp_args(p);
             if (!interp_layout_ok(p, b.ip)) return NFFT3_ERR_INVALID_ARG;
             b.ip.grid = grid;
@@ -185,7 +184,7 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
         for (int ax = 1; ax <= 2; ++ax) {
             const ColArgs &c = ax == 1 ? b.c1 : b.c0;
             if (b.ntile[ax] <= 0) continue;
-            const bool st = static_fft_len(c.n) && c.C == static_cols_nl<T>(c.n);
+            const bool st = col_static<T>(c);
             BatchGroup &g = group_of(ax, st ? c.n : 0);
             g.ids.push_back(t);
             g.lds = std::max(g.lds, col_lds<T>(c));

@@ -19,7 +19,6 @@
 namespace nfft3 {
 
 constexpr int kRowThreads = 256;
-constexpr int kColThreads = 512;
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kRowThreads) fft_rows_kernel(RowArgs a) {
@@ -28,9 +27,9 @@ __global__ void __launch_bounds__(kRowThreads) fft_rows_kernel(RowArgs a) {
 }
 
 template <typename T, bool FWD>
-__global__ void __launch_bounds__(kColThreads) fft_cols_kernel(ColArgs a) {
+__global__ void __launch_bounds__(kColsThreadsGeneric) fft_cols_kernel(ColArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cols_body<T, FWD, kColThreads, 16>(a, blockIdx.x, blockIdx.y, smem_raw);
+    cols_body<T, FWD, kColsThreadsGeneric, 16>(a, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // compile-time-engine passes (the lengths of static_fft_len)
@@ -41,9 +40,9 @@ __global__ void __launch_bounds__(kRowThreads) fft_rows_kernel_s(RowArgs a) {
 }
 
 template <typename T, bool FWD, int N>
-__global__ void __launch_bounds__(kColThreads) fft_cols_kernel_s(ColArgs a) {
+__global__ void __launch_bounds__(kColsThreads) fft_cols_kernel_s(ColArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cols_body_s<T, FWD, kColThreads, N, static_cols_nl<T>(N)>(a, blockIdx.x, blockIdx.y, smem_raw);
+    cols_body_s<T, FWD, kColsThreads, N, static_cols_nl<T>(N)>(a, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 template <typename T, int MODE, int N>
@@ -54,7 +53,7 @@ static void launch_rows_s(dim3 g, size_t lds, hipStream_t s, const RowArgs &a) {
 template <typename T, bool FWD, int N>
 static void launch_cols_s(dim3 g, size_t lds, hipStream_t s, const ColArgs &a) {
     allow_lds((const void *)fft_cols_kernel_s<T, FWD, N>, lds);
-    hipLaunchKernelGGL((fft_cols_kernel_s<T, FWD, N>), g, dim3(kColThreads), lds, s, a);
+    hipLaunchKernelGGL((fft_cols_kernel_s<T, FWD, N>), g, dim3(kColsThreads), lds, s, a);
 }
 
 template <typename T, int MODE>
@@ -71,7 +70,7 @@ static bool rows_static(const RowArgs &a, dim3 g, size_t lds, hipStream_t s) {
 
 template <typename T, bool FWD>
 static bool cols_static(const ColArgs &a, dim3 g, size_t lds, hipStream_t s) {
-    if (!static_fft_len(a.n) || a.C != static_cols_nl<T>(a.n)) return false;
+    if (!col_static<T>(a)) return false;
     switch (a.n) {
 #define NFFT3_COLS_LAUNCH(L) \
         case L: launch_cols_s<T, FWD, L>(g, lds, s, a); return true;
@@ -103,7 +102,7 @@ static int rows_pass(nfft3_plan_impl *p, int mode, const void *in, void *out, in
 template <typename T>
 static int cols_pass(nfft3_plan_impl *p, int axis, bool fwd, int Lin, int Lout, int64_t n_outer,
                      int64_t s_outer) {
-    ColArgs a = make_col_args<T>(p, p->grid, axis, Lin, Lout, s_outer, kColThreads, 16);
+    ColArgs a = make_col_args<T>(p, p->grid, axis, Lin, Lout, s_outer);
     dim3 grid((unsigned)col_grid_x(a), (unsigned)n_outer);
     const size_t lds = col_lds<T>(a);
     const bool done = fwd ? cols_static<T, true>(a, grid, lds, p->stream)
@@ -114,10 +113,10 @@ static int cols_pass(nfft3_plan_impl *p, int axis, bool fwd, int Lin, int Lout, 
     }
     if (fwd) {
         allow_lds((const void *)fft_cols_kernel<T, true>, lds);
-        hipLaunchKernelGGL((fft_cols_kernel<T, true>), grid, dim3(kColThreads), lds, p->stream, a);
+        hipLaunchKernelGGL((fft_cols_kernel<T, true>), grid, dim3(kColsThreadsGeneric), lds, p->stream, a);
     } else {
         allow_lds((const void *)fft_cols_kernel<T, false>, lds);
-        hipLaunchKernelGGL((fft_cols_kernel<T, false>), grid, dim3(kColThreads), lds, p->stream, a);
+        hipLaunchKernelGGL((fft_cols_kernel<T, false>), grid, dim3(kColsThreadsGeneric), lds, p->stream, a);
     }
     NFFT3_LAUNCH_CHECK("fft_cols_kernel");
     return NFFT3_OK;

@@ -204,11 +204,12 @@ __device__ __forceinline__ void fft_lines(c_t<T> *buf, int ls, int nlines, int n
     fft_stage_r<T, VMAX, NT, FWD, LINE_FAST, false, true>(rl.r[rl.nrad - 1], buf, ls, nlines, n, Ns, tw, ld, st);
 }
 
-// ------------------------------------ compile-time power-of-two engine ----
-// The same Stockham stages with n, the radices (p2_radix), the spans Ns, the
+// ------------------------------------------------ compile-time engine ----
+// The same Stockham stages with n, the radices (st_radix), the spans Ns, the
 // lines per workgroup NL and the LDS line stride LS known at compile time:
-// the index math reduces to shifts and masks, and a stage's twiddles come
-// from its own table (8 entries per k, so one butterfly's are contiguous).
+// the index math folds to constant divisions (shifts and masks for powers
+// of two), and a stage's twiddles come from its own table (8 entries per k,
+// so one butterfly's are contiguous).
 template <typename T, int N, int S, int NL, int LS, int NT, bool FWD, bool LINE_FAST, class LD, class ST>
 __device__ __forceinline__ void sfft_stage(c_t<T> *buf, const c_t<T> *__restrict__ stw, LD &ld, ST &st) {
     constexpr int R = st_radix(N, S), NS = st_ns(N, S), NRAD = st_nrad(N);
@@ -265,9 +266,22 @@ __device__ __forceinline__ void sfft_lines(c_t<T> *buf, const c_t<T> *__restrict
     if constexpr (S + 1 < st_nrad(N)) sfft_lines<T, N, S + 1, NL, LS, NT, FWD, LINE_FAST>(buf, stw, ld, st);
 }
 
-// Lengths served by the compile-time engine, and its lines per workgroup,
-// computed exactly as the host does (make_row_args / make_col_args with
-// lines_fit over the same radix plan), so both sides agree.
+// Column passes of the compile-time engine: workgroup size, and the LDS
+// bound of one tile (lines of n + 1 values).  A tile spans 256 contiguous
+// bytes of every row it visits: along axis 0 consecutive rows lie one plane
+// (n1 n2 values, 2 MB and more) apart, so each row visit is a separate page
+// translation, and 128-byte segments ran that pass at ~60% of the axis-1
+// pass's bandwidth.  The generic engine keeps 128-byte segments, 512
+// threads and an 80 KB tile (its double-precision body spills at 1024).
+constexpr int kColsThreads = 1024;
+constexpr size_t kColsLdsMax = 144 * 1024;
+constexpr int kColsThreadsGeneric = 512;
+constexpr size_t kColsLdsMaxGeneric = 80 * 1024;
+
+// Lengths served by the compile-time engine, and its lines per workgroup:
+// the row count equals what make_row_args finds with lines_fit over the same
+// radix plan, and make_col_args takes the column count from here, so host
+// and device agree.
 constexpr bool static_fft_len(int n) {
     return n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512;
 }
@@ -293,9 +307,9 @@ constexpr int static_rows_nl(int n) {
 }
 template <typename T>
 constexpr int static_cols_nl(int n) {
-    int C = 128 / (int)sizeof(c_t<T>);
-    while (C > 1 && C * (n + 1) * (int)sizeof(c_t<T>) > 80 * 1024) C /= 2;
-    const int f = st_lines_fit(n, 16, C, 512);
+    int C = 256 / (int)sizeof(c_t<T>);
+    while (C > 1 && C * (n + 1) * (int)sizeof(c_t<T>) > (int)kColsLdsMax) C /= 2;
+    const int f = st_lines_fit(n, 16, C, kColsThreads);
     return f < C ? f : C;
 }
 
@@ -556,7 +570,6 @@ inline RadixList radix_list(const FftAxisPlan &f) {
 }
 
 // Column tiles may use more than 64 KiB of LDS (gfx950 has 160 KiB per CU).
-constexpr size_t kColsLdsMax = 80 * 1024;
 
 // Row-pass arguments (mode 0: forward first pass into `grid`; mode 1: adjoint
 // last pass from `grid`) for workgroups of nthreads threads.
@@ -592,8 +605,7 @@ inline size_t row_lds(const RowArgs &a) { return (size_t)a.lpw * a.n * sizeof(c_
 // Column-pass arguments over `grid` for workgroups of nthreads threads with
 // at most vmax values per thread.
 template <typename T>
-inline ColArgs make_col_args(const nfft3_plan_impl *p, void *grid, int axis, int Lin, int Lout, int64_t s_outer,
-                             int nthreads, int vmax) {
+inline ColArgs make_col_args(const nfft3_plan_impl *p, void *grid, int axis, int Lin, int Lout, int64_t s_outer) {
     const FftAxisPlan &f = p->fft[axis];
     ColArgs a;
     a.data = grid;
@@ -606,14 +618,23 @@ inline ColArgs make_col_args(const nfft3_plan_impl *p, void *grid, int axis, int
     a.s_axis = axis == 0 ? p->n[1] * p->n[2] : p->n[2];
     a.s_outer = s_outer;
     a.rl = radix_list(f);
-    // 128-byte column segments, bounded by LDS and registers
+    if (static_fft_len(f.n) && static_cols_nl<T>(f.n) <= a.ncols) {
+        a.C = static_cols_nl<T>(f.n);
+        return a;
+    }
+    // generic engine: 128-byte column segments, bounded by LDS and registers
     int C = (int)(128 / sizeof(c_t<T>));
-    while (C > 1 && (size_t)C * (f.n + 1) * sizeof(c_t<T>) > kColsLdsMax) C /= 2;
-    C = std::min(C, lines_fit(f, vmax, C, nthreads));
+    while (C > 1 && (size_t)C * (f.n + 1) * sizeof(c_t<T>) > kColsLdsMaxGeneric) C /= 2;
+    C = std::min(C, lines_fit(f, 16, C, kColsThreadsGeneric));
     C = std::min<int>(C, a.ncols);
     a.C = C;
     return a;
 }
+// whether a column pass runs on the compile-time engine, and its workgroup size
+template <typename T>
+inline bool col_static(const ColArgs &a) { return static_fft_len(a.n) && a.C == static_cols_nl<T>(a.n); }
+template <typename T>
+inline int col_threads(const ColArgs &a) { return col_static<T>(a) ? kColsThreads : kColsThreadsGeneric; }
 template <typename T>
 inline size_t col_lds(const ColArgs &a) { return (size_t)a.C * (a.n + 1) * sizeof(c_t<T>); }
 inline int col_grid_x(const ColArgs &a) { return (a.ncols + a.C - 1) / a.C; }
