@@ -65,6 +65,32 @@ __device__ __forceinline__ T piece_d(const T *c, int deg, T f, T &dw) {
     return w;
 }
 
+// The window sums keep the pieces in LDS as rows of a fixed length ZC (a
+// whole number of 16-byte units, zero above the degree), so a piece is a few
+// 16-byte reads and an unrolled Horner chain; the leading zeros pass through
+// the chain exactly, so the value is the one of piece().  elt = bytes of one
+// complex element.
+constexpr int zrow_len(int elt, int W) { return elt == 8 ? 12 : (W <= 4 ? 20 : 16); }
+
+template <typename T, int ZC>
+__device__ __forceinline__ T piece_fixed(const T *c, T f) {
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int E = 16 / sizeof(T);
+    const V *cv = reinterpret_cast<const V *>(c);
+    T k[ZC];
+#pragma unroll
+    for (int u = 0; u < ZC / E; ++u) {
+        const V v = cv[u];
+#pragma unroll
+        for (int e = 0; e < E; ++e) k[u * E + e] = v[e];
+    }
+    const T y = (T)2 * f - (T)1;
+    T w = k[ZC - 1];
+#pragma unroll
+    for (int q = ZC - 2; q >= 0; --q) w = w * y + k[q];
+    return w;
+}
+
 // cell index in [0, n) and fraction of a folded coordinate
 template <typename T>
 __device__ __forceinline__ int cell_frac(double x, int n, T &frac) {
@@ -319,10 +345,16 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
     const int bufsz = it.PY * it.PXp;
     c_t<T> *buf0 = reinterpret_cast<c_t<T> *>(smem_raw);
     c_t<T> *buf1 = buf0 + bufsz;
-    T *scoef = reinterpret_cast<T *>(buf1 + bufsz);
+    // pieces: rows of ZC coefficients (16-byte aligned) when the degree fits
+    constexpr int ZC = zrow_len((int)sizeof(c_t<T>), W);
+    const bool zfix = !GRAD && a.deg < ZC;
+    const int zrow = zfix ? ZC : a.deg + 1;
+    T *scoef = reinterpret_cast<T *>(smem_raw + ((2 * (size_t)bufsz * sizeof(c_t<T>) + 15) & ~(size_t)15));
     const T *coef = (const T *)a.coef;
-    const int nc = W * (a.deg + 1);
-    for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
+    for (int i = threadIdx.x; i < W * zrow; i += kPsThreads) {
+        const int r = i / zrow, q = i - r * zrow;
+        scoef[i] = q <= a.deg ? coef[r * (a.deg + 1) + q] : (T)0;
+    }
     // the pad columns are read (with zero weight) by the pair layout: clear
     // them once; staging never writes them
     const int npad = it.PXp - it.PX;
@@ -461,8 +493,10 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
             const int r0 = i - zlo[k];
             if (r0 >= 0 && r0 < W) {
                 T dw0 = 0;
-                const T w0 = GRAD ? piece_d<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k], dw0)
-                                  : piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
+                T w0;
+                if constexpr (GRAD) w0 = piece_d<T>(scoef + r0 * zrow, a.deg, f0[k], dw0);
+                else if (zfix) w0 = piece_fixed<T, ZC>(scoef + r0 * ZC, f0[k]);
+                else w0 = piece<T>(scoef + r0 * zrow, a.deg, f0[k]);
                 T sr = 0, si = 0;
                 T ur = 0, ui = 0, vr2 = 0, vi2 = 0;      // GRAD: sum d1 c, sum w1 q
                 // Reads are software-pipelined in chunks of CH units of a
@@ -635,11 +669,13 @@ inline bool interp_layout_ok(const nfft3_plan_impl *p, const PSArgs &a) {
     return !(p->elt == 16 && p->m == 8) || a.pxp == p->bins.Bx + 2 * p->m - 1;
 }
 
-// LDS bytes of the interp kernel: two staged planes + the coefficients.
+// LDS bytes of the interp kernel: two staged planes + the coefficient rows
+// (16-byte aligned, zrow_len long when the degree fits).
 inline size_t interp_lds(const nfft3_plan_impl *p, const PSArgs &a) {
     const int W = 2 * p->m;
     const size_t bufsz = (size_t)(p->bins.By + W - 1) * a.pxp;
-    return 2 * bufsz * p->elt + (size_t)W * (p->deg + 1) * (p->elt / 2);
+    const int zrow = std::max(zrow_len(p->elt, W), p->deg + 1);
+    return ((2 * bufsz * p->elt + 15) & ~(size_t)15) + (size_t)W * zrow * (p->elt / 2);
 }
 
 // LDS bytes of the window-sum kernels: nbuf staged planes + the coefficients.
