@@ -46,24 +46,28 @@ grad_ps_kernel(PSArgs a) {
 // ------------------------------------------------------------ spread ----
 // The plane accumulator in LDS holds 64-bit fixed-point values: on gfx950 an
 // LDS float atomic add runs ~15x slower than an LDS 64-bit integer atomic
-// add (measured), whatever the address pattern.  A chunk of at most 256
-// points is accumulated at scale 2^k with 2^k max|f| < 2^53, so every
-// contribution |f w0 w1 w2| 2^k (window values <= 1) is below 2^53 and any
-// sum of at most 256 of them stays below 2^61; a contribution is rounded to
-// the nearest integer, an error of at most 2^-54 max|f| (half an FP64 ulp of
-// the chunk's largest value).  Each flushed plane is converted back (exact
-// power-of-two scaling) and added to the grid with global atomics.
+// add (measured), whatever the address pattern.  A chunk of at most 512
+// points (PPT per thread; slot k of thread t is sorted index lo + k 256 + t)
+// is accumulated at scale 2^k with 2^k max|f| < 2^53, so every contribution
+// |f w0 w1 w2| 2^k (window values <= 1) is below 2^53 and any sum of at most
+// 512 of them stays below 2^62; a contribution is rounded to the nearest
+// integer, an error of at most 2^-54 max|f| (half an FP64 ulp of the chunk's
+// largest value).  Each plane is flushed once per chunk: converted back
+// (exact power-of-two scaling) and added to the grid with global atomics,
+// whose rate bounds the complex<float> form, hence two points per thread
+// there (one walk and one flush per 512-point item).
 __device__ __forceinline__ long long fixed_round(double x) { return __double2ll_rn(x); }
 
-template <typename T, int W>
+template <typename T, int W, int PPT>
 __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     constexpr int m = W / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ float wmax[kPsThreads / 64];
     const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
-    for (int lo = item.y; lo < item.z; lo += kPsThreads) {
+    for (int lo = item.y; lo < item.z; lo += kPsThreads * PPT) {
     __syncthreads();
-    const PSItem it = ps_range(a, m, item.x, lo, min(item.z, lo + kPsThreads));
+    const int hi = min(item.z, lo + kPsThreads * PPT);
+    const PSItem it = ps_range(a, m, item.x, lo, hi);
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);   // (re, im) per element
     T *scoef = reinterpret_cast<T *>(acc + 2 * it.psz);
     const T *coef = (const T *)a.coef;
@@ -71,27 +75,37 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
     for (int e = threadIdx.x; e < 2 * it.psz; e += kPsThreads) acc[e] = 0ull;
 
-    T w1[W], w2[W];
-    T f0 = 0;
-    int zc = 0, yo = 0, xo = 0;
-    c_t<T> v = cmk<T>(0, 0);
-    if (it.active) {
-        const double *xp = a.xs + 3 * it.p;
-        T f1, f2;
-        zc = cell_frac<T>(xp[0], a.n0, f0);
-        const int yc = cell_frac<T>(xp[1], a.n1, f1);
-        const int xc = cell_frac<T>(xp[2], a.n2, f2);
-        yo = yc - it.y0;
-        xo = xc - it.x0;
-        window_weights<T, W>(f1, coef, a.deg, w1);
-        window_weights<T, W>(f2, coef, a.deg, w2);
-        v = ((const c_t<T> *)a.vals)[a.perm[it.p]];
+    T w1[PPT][W], w2[PPT][W];
+    T f0[PPT];
+    int zlo[PPT], base[PPT];
+    c_t<T> v[PPT];
+    float amax = 0.f;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int pk = lo + k * kPsThreads + threadIdx.x;
+        f0[k] = 0;
+        zlo[k] = -4 * W;     // never active
+        base[k] = 0;
+        v[k] = cmk<T>(0, 0);
+#pragma unroll
+        for (int r = 0; r < W; ++r) { w1[k][r] = 0; w2[k][r] = 0; }
+        if (pk < hi) {
+            const double *xp = a.xs + 3 * pk;
+            T f1, f2;
+            const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
+            const int yc = cell_frac<T>(xp[1], a.n1, f1);
+            const int xc = cell_frac<T>(xp[2], a.n2, f2);
+            zlo[k] = zc - m + 1 - it.zbeg;
+            base[k] = 2 * ((yc - it.y0) * it.PX + (xc - it.x0));
+            window_weights<T, W>(f1, coef, a.deg, w1[k]);
+            window_weights<T, W>(f2, coef, a.deg, w2[k]);
+            v[k] = ((const c_t<T> *)a.vals)[a.perm[pk]];
+            amax = fmaxf(amax, (float)fmax(fabs((double)v[k].x), fabs((double)v[k].y)));
+        }
     }
     // chunk scale 2^k: 2^k max|f| < 2^53
-    float amax = it.active ? (float)fmax(fabs((double)v.x), fabs((double)v.y)) : 0.f;
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
-    const int zlo = zc - m + 1 - it.zbeg;
     constexpr int NF = ps_nf<W>();
     int off[NF], lidx[NF];
     ps_offsets<NF>(a, it, m, off, lidx);
@@ -103,25 +117,30 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     for (int w = 0; w < kPsThreads / 64; ++w) bmax = fmaxf(bmax, wmax[w]);
     int ex = 0;
     if (bmax > 0.f) frexpf(bmax * 1.0001f, &ex);   // bmax < 2^ex (float rounding of |f| covered)
-    const int k = 52 - ex;
-    const double vr0 = ldexp((double)v.x, k), vi0 = ldexp((double)v.y, k);
-    double w2d[W];
+    const int ks = 52 - ex;
+    double vr0[PPT], vi0[PPT];
 #pragma unroll
-    for (int r = 0; r < W; ++r) w2d[r] = (double)w2[r];
+    for (int k = 0; k < PPT; ++k) {
+        vr0[k] = ldexp((double)v[k].x, ks);
+        vi0[k] = ldexp((double)v[k].y, ks);
+    }
 
     for (int i = 0; i < it.nplanes; ++i) {
-        const int r0 = i - zlo;
-        if (it.active && r0 >= 0 && r0 < W) {
-            const double w0 = (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0);
-            const double vr = w0 * vr0, vi = w0 * vi0;
-            unsigned long long *base = acc + 2 * (yo * it.PX + xo);
-            for (int r1 = 0; r1 < W; ++r1) {
-                unsigned long long *row = base + 2 * r1 * it.PX;
-                const double br = (double)w1[r1] * vr, bi = (double)w1[r1] * vi;
 #pragma unroll
-                for (int r2 = 0; r2 < W; ++r2) {
-                    atomicAdd(&row[2 * r2], (unsigned long long)fixed_round(w2d[r2] * br));
-                    atomicAdd(&row[2 * r2 + 1], (unsigned long long)fixed_round(w2d[r2] * bi));
+        for (int k = 0; k < PPT; ++k) {
+            const int r0 = i - zlo[k];
+            if (r0 >= 0 && r0 < W) {
+                const double w0 = (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
+                const double vr = w0 * vr0[k], vi = w0 * vi0[k];
+                for (int r1 = 0; r1 < W; ++r1) {
+                    unsigned long long *row = acc + base[k] + 2 * r1 * it.PX;
+                    const double br = (double)w1[k][r1] * vr, bi = (double)w1[k][r1] * vi;
+#pragma unroll
+                    for (int r2 = 0; r2 < W; ++r2) {
+                        const double w2d = (double)w2[k][r2];
+                        atomicAdd(&row[2 * r2], (unsigned long long)fixed_round(w2d * br));
+                        atomicAdd(&row[2 * r2 + 1], (unsigned long long)fixed_round(w2d * bi));
+                    }
                 }
             }
         }
@@ -134,8 +153,8 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
             if (e < it.psz) {
                 const long long sr = (long long)acc[2 * e], si = (long long)acc[2 * e + 1];
                 if (sr != 0 || si != 0) {
-                    unsafeAtomicAdd(&grid[zoff + off[kk]].x, (T)ldexp((double)sr, -k));
-                    unsafeAtomicAdd(&grid[zoff + off[kk]].y, (T)ldexp((double)si, -k));
+                    unsafeAtomicAdd(&grid[zoff + off[kk]].x, (T)ldexp((double)sr, -ks));
+                    unsafeAtomicAdd(&grid[zoff + off[kk]].y, (T)ldexp((double)si, -ks));
                     acc[2 * e] = 0ull;
                     acc[2 * e + 1] = 0ull;
                 }
@@ -194,8 +213,12 @@ static int spread_w(nfft3_plan_impl *p, const void *f, void *grid) {
     // 16 bytes (two 64-bit fixed-point values) per staged element + the coefficients
     const size_t psz = (size_t)(p->bins.By + W - 1) * (p->bins.Bx + W - 1);
     const size_t lds = psz * 16 + (size_t)W * (p->deg + 1) * sizeof(T);
-    allow_lds((const void *)spread_ps_kernel<T, W>, lds);
-    hipLaunchKernelGGL((spread_ps_kernel<T, W>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds, p->stream, a);
+    // complex<float> up to m = 4: two points per thread (flush-bound);
+    // otherwise one (registers; complex<double> is bound by the LDS atomics)
+    constexpr int PPT = sizeof(T) == 4 && W <= 8 ? 2 : 1;
+    allow_lds((const void *)spread_ps_kernel<T, W, PPT>, lds);
+    hipLaunchKernelGGL((spread_ps_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
+                       p->stream, a);
     NFFT3_LAUNCH_CHECK("spread_ps_kernel");
     return NFFT3_OK;
 }
