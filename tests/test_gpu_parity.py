@@ -151,6 +151,49 @@ def test_stage_spread_matches_numpy(nf, dtype):
     assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,items", [(1, 512), (2, 256), (3, 512), (4, 256), (4, 512), (5, 512), (8, 256),
+                                     (8, 512)])
+def test_stage_spread_every_m_and_items(nf, m, items, dtype):
+    """The spread kernel takes one or two points per thread depending on the
+    form and m, and walks each work item in 512-point chunks: ragged item
+    sizes, both item settings, clustered and uniform points."""
+    N, M = (24, 20, 30), 2300
+    log(f"stage_spread N={N} m={m} items={items} M={M} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_tuning(16, items)
+    x = np.concatenate([rand_points(M // 2, 80 + m),
+                        workloads.wrap(-0.2 + 0.02 * np.random.default_rng(90 + m).standard_normal((M - M // 2, 3)))])
+    r = np.random.default_rng(100 + m)
+    f = r.standard_normal(M) + 1j * r.standard_normal(M)
+    p.set_points(to_dev(x))
+    p.stage_spread(to_dev(f, dtype))
+    got = p.grid().cpu().numpy()
+    ref = ns.spread(f, x, p.n, m, 2.0) / phi0(m, 2.0) ** 3
+    l2, li = rel(got, ref)
+    assert l2 < stage_tol(m, dtype), (l2, li)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_stage_spread_pileup_and_dynamic_range(nf, dtype):
+    """1500 points inside one grid cell (every chunk adds up to 512
+    contributions to the same LDS cells: the fixed-point headroom) with
+    values spread over eight orders of magnitude (one chunk scale)."""
+    m, M = 4, 1500
+    N = (16, 16, 16)
+    log(f"stage_spread pile-up N={N} m={m} M={M} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    r = np.random.default_rng(120)
+    x = workloads.wrap(10.0 / 32 + 0.001 + r.random((M, 3)) / 64)   # inside cell 10 of the n = 32 grid
+    f = (r.standard_normal(M) + 1j * r.standard_normal(M)) * 10.0 ** r.uniform(-8, 0, M)
+    p.set_points(to_dev(x))
+    p.stage_spread(to_dev(f, dtype))
+    got = p.grid().cpu().numpy()
+    ref = ns.spread(f, x, p.n, m, 2.0) / phi0(m, 2.0) ** 3
+    l2, li = rel(got, ref)
+    assert l2 < stage_tol(m, dtype), (l2, li)
+
+
 # ---------------------------------------------------------- end to end ----
 
 @pytest.mark.parametrize("dtype", DTYPES)
