@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# vector FMA peak without packed FP32 (the build disables packed FP32 ops):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz; FP64 runs at the same rate
+VALU_PEAK_TFS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (published, packed)
 
@@ -83,6 +86,25 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint / point-gradient / batched / autograd measurements")
     return ap.parse_args()
+
+
+def copy_bandwidth(torch, dev, stream, mib=1024, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB
+    (read + write bytes / time, HIP events)."""
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2.0 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def bench_batched(nf, torch, dev, workloads, stream):
@@ -186,6 +208,8 @@ def main():
         del a, b
 
     stream = torch.cuda.current_stream(dev)
+    copy_gbs = copy_bandwidth(torch, dev, stream)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     results = {}
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     for form in forms:
@@ -297,6 +321,14 @@ def main():
     else:
         dom, ms_dom, bytes_dom = "grid (deconvolve + pruned 3-D FFT)", r["ms_grid"], fft_bytes
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+    # the window sums as an arithmetic kernel: every stencil term is a real
+    # weight times a complex value (2 FMAs = 4 flops), (2m)^3 terms per point
+    interp_flops = M * (2 * r["m"]) ** 3 * 4.0
+    alu = None
+    if dom.startswith("interp"):
+        tfs = interp_flops / (ms_dom * 1e-3) / 1e12
+        alu = {"bound": "alu", "achieved": tfs, "peak": VALU_PEAK_TFS, "unit": "TFLOP/s",
+               "frac": tfs / VALU_PEAK_TFS, "flops_per_launch": interp_flops}
     line = {
         "metric": "NFFT points/sec at N=256^3, M=1e7 (FP32 m=4 vs FP64 m=8) at stated rel-l2 error",
         "value": M / (r["ms_step"] * 1e-3),
@@ -317,7 +349,8 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(main_form) if dom.startswith("interp") else None,
-                     "alg_bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom},
+                     "alg_bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom,
+                     "achievable_copy_gbs": copy_gbs, "frac_of_achievable": achieved / copy_gbs, "alu": alu},
         "cpu_baseline": cpu,
         "forms": {},
     }

@@ -263,9 +263,10 @@ static int alloc_bins(nfft3_plan_impl *p, int T) {
     const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
     const int64_t nb = ntiles * p->n[0];
     p->bins.nbins = nb;
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nb));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nb + 1)));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nb / 1024 + 2)));
+    const int64_t nc = nb * kBinCopies;
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nc));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nc + 1)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nc / 1024 + 2)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * ntiles));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (ntiles + 1)));
     return NFFT3_OK;

@@ -114,13 +114,20 @@ constexpr int kItemPts = 256;
 constexpr int kItemZ = 64;
 constexpr int kMaxPlane = 12 * kItemPts;   // staged plane elements per workgroup
 constexpr int kMaxTile = 32;               // By, Bx never exceed this
+// The counting sort keeps kBinCopies counters per (tile, z) bin, interleaved
+// (bin b, copy c at b kBinCopies + c), a workgroup using copy blockIdx mod
+// kBinCopies: clustered points send hundreds of atomic increments to the same
+// bins, and spreading them over copies divides that contention.  Each point's
+// rank is within its copy; the scan over all counters keeps a bin's copies
+// contiguous, so a bin still owns one contiguous range of sorted points.
+constexpr int kBinCopies = 8;
 
 struct Bins {
     int By = 32, Bx = 32;     // tile size in cells (y, x)
     int nty = 0, ntx = 0;     // tiles per axis
     int64_t nbins = 0;        // nty * ntx * n0
-    int *counts = nullptr;    // per-bin point counts (device)
-    int *offsets = nullptr;   // exclusive scan of counts, nbins + 1 entries (device)
+    int *counts = nullptr;    // point counts, kBinCopies counters per bin (device)
+    int *offsets = nullptr;   // exclusive scan of counts, nbins kBinCopies + 1 entries (device)
     int *scratch = nullptr;   // block sums of the scans
     int *tile_items = nullptr;      // items per tile (device)
     int *tile_item_off = nullptr;   // exclusive scan, ntiles + 1 entries (device)

@@ -57,8 +57,10 @@ bin_count_kernel(const double *__restrict__ x, int64_t M, BinGeom g, int *__rest
     } else {
         atomicOr(flag, 1);
     }
-    bin_of[j] = b;
-    rank[j] = atomicAdd(&counts[b], 1);
+    // counter copy of this workgroup (see kBinCopies)
+    const int c = b * kBinCopies + (int)(blockIdx.x & (kBinCopies - 1));
+    bin_of[j] = c;
+    rank[j] = atomicAdd(&counts[c], 1);
 }
 
 // ---- exclusive scan: block-local scans, a scan of block sums, then add ------
@@ -154,17 +156,18 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
 // counts the items of each tile, WRITE=true emits (tile, p_lo, p_hi, 0).
 template <bool WRITE>
 __global__ void __launch_bounds__(256)
-items_kernel(const int *__restrict__ counts, const int *__restrict__ offsets, int ntiles, int n0, int maxpts,
-             int *__restrict__ item_count, const int *__restrict__ item_offset, int4 *__restrict__ items) {
+items_kernel(const int *__restrict__ offsets, int ntiles, int n0, int maxpts, int *__restrict__ item_count,
+             const int *__restrict__ item_offset, int4 *__restrict__ items) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
-    const int *cnt = counts + (int64_t)tile * n0;
-    const int *off = offsets + (int64_t)tile * n0;
+    // bin (tile, z) spans offsets[(tile n0 + z) K] .. offsets[(tile n0 + z + 1) K]
+    const int *ofs = offsets + (int64_t)tile * n0 * kBinCopies;
     int k = 0;
     int64_t w = WRITE ? item_offset[tile] : 0;
     int cur = 0, z_start = 0, p_start = 0;
     for (int z = 0; z < n0; ++z) {
-        const int c = cnt[z];
+        const int oz = ofs[z * kBinCopies];
+        const int c = ofs[(z + 1) * kBinCopies] - oz;
         if (c == 0) continue;
         if (cur > 0 && (cur + c > maxpts || z - z_start >= kItemZ)) {
             if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
@@ -173,12 +176,12 @@ items_kernel(const int *__restrict__ counts, const int *__restrict__ offsets, in
         }
         if (c > maxpts) {     // a dense cell on its own
             for (int s = 0; s < c; s += maxpts) {
-                if (WRITE) items[w + k] = make_int4(tile, off[z] + s, off[z] + min(c, s + maxpts), 0);
+                if (WRITE) items[w + k] = make_int4(tile, oz + s, oz + min(c, s + maxpts), 0);
                 ++k;
             }
             continue;
         }
-        if (cur == 0) { z_start = z; p_start = off[z]; }
+        if (cur == 0) { z_start = z; p_start = oz; }
         cur += c;
     }
     if (cur > 0) {
@@ -194,7 +197,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     g.in0 = (int)p->n[0]; g.in1 = (int)p->n[1]; g.in2 = (int)p->n[2];
     g.By = p->bins.By; g.Bx = p->bins.Bx;
     g.nty = p->bins.nty; g.ntx = p->bins.ntx;
-    const int64_t nb = p->bins.nbins;
+    const int64_t nb = p->bins.nbins * kBinCopies;   // counters: kBinCopies per bin
     const int ntiles = p->bins.nty * p->bins.ntx;
     hipStream_t s = p->stream;
     hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, p->bins.counts, nb, 0);
@@ -216,7 +219,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     }
     // work items
     const unsigned tb = (unsigned)((ntiles + 255) / 256);
-    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(256), 0, s, p->bins.counts, p->bins.offsets, ntiles,
+    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(256), 0, s, p->bins.offsets, ntiles,
                        g.in0, p->sub.maxpts, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr);
     NFFT3_LAUNCH_CHECK("items_kernel");
     rc = exclusive_scan(s, p->bins.tile_items, p->bins.tile_item_off, p->bins.scratch, ntiles);
@@ -234,7 +237,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     }
     p->sub.count = nitems;
     if (nitems > 0) {
-        hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(256), 0, s, p->bins.counts, p->bins.offsets, ntiles,
+        hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(256), 0, s, p->bins.offsets, ntiles,
                            g.in0, p->sub.maxpts, (int *)nullptr, (const int *)p->bins.tile_item_off, p->sub.items);
         NFFT3_LAUNCH_CHECK("items_kernel");
     }
