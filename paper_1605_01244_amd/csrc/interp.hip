@@ -48,11 +48,11 @@ grad_ps_kernel(PSArgs a) {
 // LDS float atomic add runs ~15x slower than an LDS 64-bit integer atomic
 // add (measured), whatever the address pattern.  A chunk of at most 512
 // points (PPT per thread; slot k of thread t is sorted index lo + k 256 + t)
-// is accumulated at scale 2^k with 2^k max|f| < 2^53, so every contribution
-// |f w0 w1 w2| 2^k (window values <= 1) is below 2^53 and any sum of at most
-// 512 of them stays below 2^62; a contribution is rounded to the nearest
-// integer, an error of at most 2^-54 max|f| (half an FP64 ulp of the chunk's
-// largest value).  Each plane is flushed once per chunk: converted back
+// is accumulated at scale 2^k, k = 52 - e with max|f| < 2^e, so every
+// contribution |f w0 w1 w2| 2^k (window values <= 1) is below 2^52 and any
+// sum of at most 512 of them stays below 2^61; a contribution is rounded to
+// the nearest integer, an error of at most 2^(e-53) <= 2^-52 max|f| (one FP64
+// ulp of the chunk's largest value).  Each plane is flushed once per chunk: converted back
 // (exact power-of-two scaling) and added to the grid with global atomics,
 // whose rate bounds the complex<float> form, hence two points per thread
 // there (one walk and one flush per 512-point item).
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
             amax = fmaxf(amax, (float)fmax(fabs((double)v[k].x), fabs((double)v[k].y)));
         }
     }
-    // chunk scale 2^k: 2^k max|f| < 2^53
+    // chunk scale 2^ks: 2^ks max|f| < 2^52
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
     constexpr int NF = ps_nf<W>();
