@@ -60,7 +60,8 @@ def _load():
     lib.oracle_ndft_trafo.argtypes = [i64p, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
     lib.oracle_ndft_grad.argtypes = [i64p, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
     lib.oracle_ndft_adjoint.argtypes = [i64p, ctypes.c_int64, dp, dp, dp, ctypes.c_int]
-    for fn in (lib.oracle_ndft_trafo, lib.oracle_ndft_grad, lib.oracle_ndft_adjoint):
+    lib.oracle_ndft_adjoint_at.argtypes = [i64p, ctypes.c_int64, dp, dp, ctypes.c_int64, i64p, dp, ctypes.c_int]
+    for fn in (lib.oracle_ndft_trafo, lib.oracle_ndft_grad, lib.oracle_ndft_adjoint, lib.oracle_ndft_adjoint_at):
         fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -125,6 +126,26 @@ def ndft_adjoint(f: np.ndarray, x: np.ndarray, N, threads: int | None = None) ->
                                      _dptr(out.view(np.float64)), threads or default_threads())
     if rc:
         raise RuntimeError(f"oracle_ndft_adjoint failed ({rc})")
+    return out
+
+
+def ndft_adjoint_at(f: np.ndarray, x: np.ndarray, N, kidx, threads: int | None = None) -> np.ndarray:
+    """fhat at sampled coefficients: out[q] = sum_j f_j exp(+2 pi i k_q.x_j) for
+    the array-index triples ``kidx`` (K, 3) (frequency = index - N/2); the
+    same sum as ``ndft_adjoint``, evaluated for K coefficients over all points."""
+    N = _shape3(N)
+    x = _points(x)
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.complex128).reshape(-1))
+    if f.shape[0] != x.shape[0]:
+        raise ValueError("f and x disagree on M")
+    kidx = np.ascontiguousarray(np.asarray(kidx, dtype=np.int64).reshape(-1, 3))
+    out = np.zeros(kidx.shape[0], dtype=np.complex128)
+    rc = _load().oracle_ndft_adjoint_at(N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), x.shape[0], _dptr(x),
+                                        _dptr(f.view(np.float64)), kidx.shape[0],
+                                        kidx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        _dptr(out.view(np.float64)), threads or default_threads())
+    if rc:
+        raise RuntimeError(f"oracle_ndft_adjoint_at failed ({rc})")
     return out
 
 

@@ -33,6 +33,9 @@
  *
  * Threads: points (trafo, grad) or slabs of k0 (adjoint) are split over
  * POSIX threads; every output element is written by exactly one thread.
+ * The sampled adjoint (a few coefficients, many points) splits the points;
+ * each thread sums its points into its own row of partial sums, and the rows
+ * are added in thread order.
  */
 #include <math.h>
 #include <pthread.h>
@@ -254,5 +257,73 @@ int oracle_ndft_adjoint(const int64_t N[3], int64_t M, const double *x, const do
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, adjoint_worker, &jobs[t]);
     adjoint_worker(&jobs[0]);
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* ---- sampled type 1: fhat at K given indices, sum over all points ------- */
+/* k x mod 1 with the exact reduction of phase_vector                        */
+static double reduced_phase(double k, double x)
+{
+    double p = k * x;
+    double e = fma(k, x, -p);
+    return (p - rint(p)) + e;
+}
+
+typedef struct {
+    const int64_t *N, *kidx;
+    const double *x, *f;
+    int64_t K, j0, j1;
+    double *acc;           /* 2 K partial sums of this thread           */
+} atjob_t;
+
+static void *adjoint_at_worker(void *arg)
+{
+    atjob_t *jb = (atjob_t *)arg;
+    for (int64_t j = jb->j0; j < jb->j1; ++j) {
+        const double *xj = jb->x + 3 * j;
+        const double fr = jb->f[2 * j], fi = jb->f[2 * j + 1];
+        for (int64_t q = 0; q < jb->K; ++q) {
+            double r = 0.0;
+            for (int d = 0; d < 3; ++d)
+                r += reduced_phase((double)(jb->kidx[3 * q + d] - jb->N[d] / 2), xj[d]);
+            r -= rint(r);
+            const double c = cos(TWO_PI * r), sn = sin(TWO_PI * r);   /* exp(+2 pi i k.x) */
+            jb->acc[2 * q] += fr * c - fi * sn;
+            jb->acc[2 * q + 1] += fr * sn + fi * c;
+        }
+    }
+    return NULL;
+}
+
+/* out[q] = sum_j f_j exp(+2 pi i k_q . x_j) for the K array-index triples
+ * kidx[3q .. 3q+2] (frequency k_d = kidx - N_d/2). */
+int oracle_ndft_adjoint_at(const int64_t N[3], int64_t M, const double *x, const double *f, int64_t K,
+                           const int64_t *kidx, double *out, int nthreads)
+{
+    if (check_args(N, M) || K < 0) return -1;
+    for (int64_t q = 0; q < K; ++q)
+        for (int d = 0; d < 3; ++d)
+            if (kidx[3 * q + d] < 0 || kidx[3 * q + d] >= N[d]) return -1;
+    memset(out, 0, sizeof(double) * 2 * K);
+    if (M == 0 || K == 0) return 0;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((int64_t)nthreads > M) nthreads = (int)M;
+    double *acc = calloc((size_t)nthreads * 2 * K, sizeof(double));
+    if (!acc) return -2;
+    pthread_t th[256];
+    atjob_t jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].N = N; jobs[t].kidx = kidx; jobs[t].x = x; jobs[t].f = f; jobs[t].K = K;
+        jobs[t].j0 = M * t / nthreads;
+        jobs[t].j1 = M * (t + 1) / nthreads;
+        jobs[t].acc = acc + (size_t)t * 2 * K;
+    }
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, adjoint_at_worker, &jobs[t]);
+    adjoint_at_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    for (int t = 0; t < nthreads; ++t)
+        for (int64_t i = 0; i < 2 * K; ++i) out[i] += acc[(size_t)t * 2 * K + i];
+    free(acc);
     return 0;
 }

@@ -6,7 +6,9 @@ direct-sum oracle (which is too slow for every output at these sizes).
   plus the interpolation property at the sub-box points that coincide with
   coarse nodes (the series reproduces the sampled field there, Sec. 2).
 * N = 256^3, M = 1e7 (half uniform, half in 16 clusters), FP32 m = 4 and
-  FP64 m = 8 on the same inputs, in the launch configuration bench.py times.
+  FP64 m = 8 on the same inputs, in the launch configuration bench.py times:
+  trafo on sampled points, the adjoint on sampled coefficients, the point
+  gradient on sampled points.
 * 64 coefficient sets of N in {64, 96, 128}^3 with lognormal point counts,
   each with its three derivative fields, batched; batched = sequential and
   sampled outputs vs the oracle.
@@ -88,6 +90,57 @@ def test_powerlaw_256_1e7(nf, powerlaw_case, dtype, m):
     assert torch.isfinite(torch.view_as_real(f)).all()
     plan.close()
     del f
+    _free()
+
+
+@pytest.mark.parametrize("dtype,m", [("c64", 4), ("c128", 8)])
+def test_powerlaw_256_1e7_adjoint_and_point_gradient(nf, powerlaw_case, dtype, m):
+    """The backward calls at the full size: the adjoint of 1e7 seeded values
+    on 16 coefficients (the 8 corners of I_N and 8 seeded) against the
+    oracle's direct sum over all points, and the point gradient on 300
+    sampled points against the oracle's derivative sums."""
+    import torch
+    fhat, x = powerlaw_case
+    M, N = x.shape[0], fhat.shape
+    log(f"adjoint + point gradient N=256^3 M=1e7 {dtype} m={m}")
+    plan = nf.Plan(N, m=m, dtype=torch_dtype(dtype), device="cuda:0")
+    plan.set_points(to_dev(x))
+    r = np.random.default_rng(307)
+    w = (r.standard_normal(M) + 1j * r.standard_normal(M)) / np.sqrt(2.0)
+    wd = to_dev(w, dtype)
+    g = plan.adjoint(wd)
+    corners = np.array([[a, b, c] for a in (0, N[0] - 1) for b in (0, N[1] - 1) for c in (0, N[2] - 1)])
+    rk = np.random.default_rng(308)
+    kidx = np.concatenate([corners, np.stack([rk.integers(0, n, 8) for n in N], axis=1)])
+    got = g[tuple(torch.from_numpy(kidx[:, d]).to(g.device) for d in range(3))].cpu().numpy()
+    ref = oracle.ndft_adjoint_at(w, x, N, kidx)
+    l2, li = rel(got, ref)
+    log(f"  adjoint (16 coefficients) rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    gate = 1e-12 if dtype == "c128" else 2e-6
+    assert l2 <= gate and li <= gate
+    del g
+    gx = plan.grad_points(to_dev(fhat, dtype), wd)
+    s = workloads.sample_indices(M, 300, 309)
+    got = gx[torch.from_numpy(s).to(gx.device)].cpu().numpy()
+    D = oracle.ndft_grad(fhat, x[s])
+    ref = (np.conj(w[s])[:, None] * D).real
+    l2, li = rel(got, ref)
+    log(f"  point gradient (300 points) rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    # The gradient is the derivative of the computed windowed sum, so its
+    # error is the derivative of the value error e(x), whose content reaches
+    # the oversampled grid's band edge n_d / 2: Bernstein's inequality bounds
+    # it by pi n_d max|e| <= pi n_d gate max|f|, times |w_j| for point j
+    # (max|f| estimated on the sampled points).  FP32 rounding of the grid is
+    # white up to n_d / 2, while this |k|^-2 field's gradient is only ~46
+    # max|f|, so relative to the gradient the FP32 error is ~1e-5.
+    fmax = np.abs(oracle.ndft_trafo(fhat, x[s])).max()
+    bound = np.pi * max(plan.n) * gate * fmax
+    err = np.abs(got - ref).max(axis=1)
+    aw = np.abs(w[s])
+    assert np.all(err <= bound * aw), (err / aw).max() / bound
+    assert np.sqrt(np.mean(err ** 2)) <= bound * np.sqrt(np.mean(aw ** 2))
+    plan.close()
+    del gx, wd
     _free()
 
 

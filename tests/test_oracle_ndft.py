@@ -217,6 +217,32 @@ def test_adjoint_brute_force():
     assert np.max(np.abs(oracle.ndft_adjoint(y, x, N) - ref)) < 1e-13
 
 
+def test_adjoint_at_sampled_coefficients():
+    """The sampled adjoint: the single-point closed form at every corner of
+    I_N and at random indices, and agreement with the full adjoint (a
+    separate code path: per-axis exponential tables, slabs of k0) on many
+    points, including large |k| where phase reduction matters."""
+    N = (16, 12, 256)
+    corners = np.array([[a, b, c] for a in (0, N[0] - 1) for b in (0, N[1] - 1) for c in (0, N[2] - 1)])
+    r = np.random.default_rng(46)
+    kidx = np.concatenate([corners, np.stack([r.integers(0, n, 10) for n in N], axis=1)])
+    x = _rand_points(1, 47) * 1000.0 + 0.123456789      # far outside the box: folding by the phase itself
+    out = oracle.ndft_adjoint_at(np.ones(1), x, N, kidx)
+    k = kidx - np.array(N) // 2
+    ref = np.array([cmath.exp(2j * math.pi * math.fsum(float(k[q, d]) * float(x[0, d]) for d in range(3)))
+                    for q in range(len(kidx))])
+    # the reference phase itself carries the rounding of k.x at |x| ~ 1e3
+    assert np.max(np.abs(out - ref)) < 1e-9
+    x = _rand_points(3000, 48)
+    y = r.standard_normal(3000) + 1j * r.standard_normal(3000)
+    full = oracle.ndft_adjoint(y, x, N)
+    got = oracle.ndft_adjoint_at(y, x, N, kidx)
+    ref = full[kidx[:, 0], kidx[:, 1], kidx[:, 2]]
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(full)) < 1e-13
+    with pytest.raises(RuntimeError):
+        oracle.ndft_adjoint_at(y, x, N, np.array([[0, 0, N[2]]]))
+
+
 # ------------------------------------------------------------- grad ----
 
 def test_grad_single_mode_closed_form():
