@@ -9,6 +9,8 @@ direct-sum oracle (which is too slow for every output at these sizes).
   FP64 m = 8 on the same inputs, in the launch configuration bench.py times:
   trafo on sampled points, the adjoint on sampled coefficients, the point
   gradient on sampled points.
+* the largest single transform (N = 512^3) and large mixed-radix shapes,
+  trafo and adjoint on samples.
 * 64 coefficient sets of N in {64, 96, 128}^3 with lognormal point counts,
   each with its three derivative fields, batched; batched = sequential and
   sampled outputs vs the oracle.
@@ -141,6 +143,51 @@ def test_powerlaw_256_1e7_adjoint_and_point_gradient(nf, powerlaw_case, dtype, m
     assert np.sqrt(np.mean(err ** 2)) <= bound * np.sqrt(np.mean(aw ** 2))
     plan.close()
     del gx, wd
+    _free()
+
+
+_large_cache = {}
+
+
+def _large_case(N):
+    """|k|^-2 coefficients of shape N and 2e5 mixed points (cached per N)."""
+    if N not in _large_cache:
+        _large_cache.clear()
+        _large_cache[N] = (workloads.powerlaw_coeffs(N, 330),
+                           workloads.mixed_points(200_000, 16, 0.02, (331, 332, 333, 334)))
+    return _large_cache[N]
+
+
+@pytest.mark.parametrize("N,dtype,m", [((512, 512, 512), "c64", 4), ((512, 512, 512), "c128", 8),
+                                       ((500, 250, 120), "c128", 6), ((250, 480, 96), "c64", 4)])
+def test_large_and_mixed_radix_sizes(nf, N, dtype, m):
+    """The largest single transform (N = 512^3: n = 1024 on the generic FFT
+    engine, a 17 GB FP64 grid) and large mixed-radix shapes (n = 1000 / 500 /
+    240 and 500 / 960 / 192, tiles cut by the grid edge): trafo on 40 sampled
+    points and the adjoint on the 8 corner coefficients against the oracle."""
+    import torch
+    fhat, x = _large_case(N)
+    log(f"large N={N} {dtype} m={m} M={x.shape[0]}")
+    plan = nf.Plan(N, m=m, dtype=torch_dtype(dtype), device="cuda:0")
+    plan.set_points(to_dev(x))
+    f = plan.trafo(to_dev(fhat, dtype))
+    s = workloads.sample_indices(x.shape[0], 40, 335)
+    got = f[torch.from_numpy(s).to(f.device)].cpu().numpy()
+    l2, li = rel(got, oracle.ndft_trafo(fhat, x[s]))
+    log(f"  trafo (40 points) rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    gate = tol(m, 2.0, dtype)
+    assert l2 <= gate and li <= gate
+    del f
+    r = np.random.default_rng(336)
+    w = r.standard_normal(x.shape[0]) + 1j * r.standard_normal(x.shape[0])
+    g = plan.adjoint(to_dev(w, dtype))
+    kidx = np.array([[a, b, c] for a in (0, N[0] - 1) for b in (0, N[1] - 1) for c in (0, N[2] - 1)])
+    got = g[tuple(torch.from_numpy(kidx[:, d]).to(g.device) for d in range(3))].cpu().numpy()
+    l2, li = rel(got, oracle.ndft_adjoint_at(w, x, N, kidx))
+    log(f"  adjoint (8 corners) rel-l2 {l2:.2e} rel-linf {li:.2e}")
+    assert l2 <= gate and li <= gate
+    plan.close()
+    del g
     _free()
 
 
