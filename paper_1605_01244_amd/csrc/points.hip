@@ -149,25 +149,45 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
     perm[pos] = (int)j;
 }
 
-// ---- work items: walk each tile column's z-cells (one thread per tile) ------
+// ---- work items: walk each tile column's z-cells (one wave per tile) ------
 // A new item starts when adding the next cell would exceed maxpts points or
 // the item would span more than kItemZ z-cells; a cell holding more than
 // maxpts points becomes ceil(count/maxpts) items of its own.  WRITE=false
 // counts the items of each tile, WRITE=true emits (tile, p_lo, p_hi, 0).
+// The wave stages the tile's n0 + 1 bin starts in LDS with coalesced loads
+// (when they fit), then one lane walks them: the walk is sequential, so
+// reading its inputs from HBM one dependent load at a time dominated.
+constexpr int kItemWaves = 4;            // tiles per workgroup
+
 template <bool WRITE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kItemWaves)
 items_kernel(const int *__restrict__ offsets, int ntiles, int n0, int maxpts, int *__restrict__ item_count,
-             const int *__restrict__ item_offset, int4 *__restrict__ items) {
-    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tile >= ntiles) return;
+             const int *__restrict__ item_offset, int4 *__restrict__ items, int use_lds) {
+    extern __shared__ int sofs[];        // kItemWaves x (n0 + 1) bin starts
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * kItemWaves + wave;
+    const bool valid = tile < ntiles;
     // bin (tile, z) spans offsets[(tile n0 + z) K] .. offsets[(tile n0 + z + 1) K]
-    const int *ofs = offsets + (int64_t)tile * n0 * kBinCopies;
+    const int *g = offsets + (int64_t)(valid ? tile : 0) * n0 * kBinCopies;
+    const int *ofs = g;
+    int stride = kBinCopies;
+    if (use_lds) {
+        int *sw = sofs + wave * (n0 + 1);
+        if (valid)
+            for (int z = lane; z <= n0; z += 64) sw[z] = g[(int64_t)z * kBinCopies];
+        __syncthreads();
+        ofs = sw;
+        stride = 1;
+    }
+    if (!valid || lane != 0) return;
     int k = 0;
     int64_t w = WRITE ? item_offset[tile] : 0;
     int cur = 0, z_start = 0, p_start = 0;
+    int onext = ofs[0];
     for (int z = 0; z < n0; ++z) {
-        const int oz = ofs[z * kBinCopies];
-        const int c = ofs[(z + 1) * kBinCopies] - oz;
+        const int oz = onext;
+        onext = ofs[(z + 1) * stride];
+        const int c = onext - oz;
         if (c == 0) continue;
         if (cur > 0 && (cur + c > maxpts || z - z_start >= kItemZ)) {
             if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
@@ -218,9 +238,12 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
         NFFT3_LAUNCH_CHECK("scatter_kernel");
     }
     // work items
-    const unsigned tb = (unsigned)((ntiles + 255) / 256);
-    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(256), 0, s, p->bins.offsets, ntiles,
-                       g.in0, p->sub.maxpts, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr);
+    const unsigned tb = (unsigned)((ntiles + kItemWaves - 1) / kItemWaves);
+    const size_t ilds = sizeof(int) * kItemWaves * ((size_t)g.in0 + 1);
+    const int use_lds = ilds <= 64 * 1024 ? 1 : 0;
+    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(64 * kItemWaves), use_lds ? ilds : 0, s, p->bins.offsets,
+                       ntiles, g.in0, p->sub.maxpts, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr,
+                       use_lds);
     NFFT3_LAUNCH_CHECK("items_kernel");
     rc = exclusive_scan(s, p->bins.tile_items, p->bins.tile_item_off, p->bins.scratch, ntiles);
     if (rc) return rc;
@@ -237,8 +260,9 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     }
     p->sub.count = nitems;
     if (nitems > 0) {
-        hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(256), 0, s, p->bins.offsets, ntiles,
-                           g.in0, p->sub.maxpts, (int *)nullptr, (const int *)p->bins.tile_item_off, p->sub.items);
+        hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(64 * kItemWaves), use_lds ? ilds : 0, s,
+                           p->bins.offsets, ntiles, g.in0, p->sub.maxpts, (int *)nullptr,
+                           (const int *)p->bins.tile_item_off, p->sub.items, use_lds);
         NFFT3_LAUNCH_CHECK("items_kernel");
     }
     return NFFT3_OK;
