@@ -129,9 +129,11 @@ int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int 
  * holds its coefficients and out_dev[t] receives (1 + popcount(deriv_mask))
  * blocks of M_t values as in nfft3_trafo_fields.  fhat_dev / out_dev are host
  * arrays of T device pointers; plans is a host array of T distinct plans.
- * The whole batch runs as four kernel launches, one per stage (row pass,
- * column pass axis 1, column pass axis 0, window sums), each covering the
- * work items of every (plan, field) pair.  Each plan keeps one grid per
+ * Each FFT stage (row pass, column pass axis 1, column pass axis 0) runs as
+ * one kernel launch per distinct transform length along its axis, the window
+ * sums as one launch; each launch covers the work items of every (plan,
+ * field) pair in its group, and the results equal the sequential
+ * nfft3_trafo_fields results bit for bit.  Each plan keeps one grid per
  * evaluated field, allocated on its first batched call with a given mask.
  * Work is enqueued on plans[0]'s stream; the call returns after it finished
  * (the launch descriptors are staged from host memory). */

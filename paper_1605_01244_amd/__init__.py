@@ -208,7 +208,8 @@ class Plan:
 
 def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0):
     """Evaluate every plan's coefficients (and derivative fields) together:
-    one launch per stage over all (plan, field) pairs.  Returns a list of
+    per stage one launch per transform length over all (plan, field) pairs
+    of that length (the window sums: one launch).  Returns a list of
     (1 + popcount(mask), M_t) tensors."""
     T = len(plans)
     if T != len(fhats):

@@ -1,4 +1,4 @@
-"""Batched evaluation (one launch per stage over all plans and fields):
+"""Batched evaluation (per stage one launch per transform length over all plans and fields):
 uneven N, own point sets, derivative fields; against sequential single-plan
 calls and the oracle."""
 import numpy as np
