@@ -70,6 +70,27 @@ def test_batch_mixed_radices(nf):
         assert l2 <= tol(4, 2.0, "c64") and li <= tol(4, 2.0, "c64")
 
 
+def test_batch_plans_with_different_tiles(nf):
+    """Plans of one batch may use different tiles (same points per item):
+    each transform keeps its own geometry."""
+    spec = [((16, 16, 16), 2500), ((24, 24, 24), 1500), ((32, 32, 32), 3000)]
+    sets = _sets(spec, 70)
+    log("batch with per-plan tiles 8 / 20 / 32")
+    plans, fh = [], []
+    for (N, f, x), tile in zip(sets, (8, 20, 32)):
+        p = nf.Plan(N, sigma=2.0, m=8, dtype=torch_dtype("c128"), device="cuda:0")
+        p.set_tuning(tile, 512)
+        p.set_points(to_dev(x))
+        plans.append(p)
+        fh.append(to_dev(f, "c128"))
+    outs = nf.batch_trafo(plans, fh, 5)
+    for t, (N, f, x) in enumerate(sets):
+        assert plans[t].tuning()[0] == (8, 20, 32)[t]
+        assert np.array_equal(outs[t].cpu().numpy(), plans[t].trafo_fields(fh[t], 5).cpu().numpy())
+        l2, li = rel(outs[t][0].cpu().numpy(), oracle.ndft_trafo(f, x))
+        assert l2 <= tol(8, 2.0, "c128") and li <= tol(8, 2.0, "c128")
+
+
 def test_batch_argument_errors(nf):
     import torch
     p1 = nf.Plan((8, 8, 8), m=4, dtype=torch.complex128, device="cuda:0")

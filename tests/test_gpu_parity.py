@@ -152,16 +152,17 @@ def test_stage_spread_matches_numpy(nf, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("m,items", [(1, 512), (2, 256), (3, 512), (4, 256), (4, 512), (5, 512), (8, 256),
-                                     (8, 512)])
-def test_stage_spread_every_m_and_items(nf, m, items, dtype):
+@pytest.mark.parametrize("m,tile,items", [(1, 16, 512), (2, 16, 256), (3, 16, 512), (4, 16, 256), (4, 16, 512),
+                                          (5, 16, 512), (8, 16, 256), (8, 16, 512), (4, 32, 512), (8, 32, 512),
+                                          (4, 8, 256), (6, 28, 512)])
+def test_stage_spread_every_m_and_items(nf, m, tile, items, dtype):
     """The spread kernel takes one or two points per thread depending on the
     form and m, and walks each work item in 512-point chunks: ragged item
-    sizes, both item settings, clustered and uniform points."""
+    sizes, both item settings, several tiles, clustered and uniform points."""
     N, M = (24, 20, 30), 2300
-    log(f"stage_spread N={N} m={m} items={items} M={M} {dtype}")
+    log(f"stage_spread N={N} m={m} tile={tile} items={items} M={M} {dtype}")
     p = make_plan(nf, N, m, dtype)
-    p.set_tuning(16, items)
+    p.set_tuning(tile, items)
     x = np.concatenate([rand_points(M // 2, 80 + m),
                         workloads.wrap(-0.2 + 0.02 * np.random.default_rng(90 + m).standard_normal((M - M // 2, 3)))])
     r = np.random.default_rng(100 + m)
@@ -360,15 +361,20 @@ def test_adjoint_dot_product_and_direct_sum(nf, N, dtype):
 # ---------------------------------------------------------------- grad ----
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_grad_points_vs_direct_derivative(nf, dtype):
+@pytest.mark.parametrize("tile,items", [(32, 512), (8, 256), (24, 512)])
+def test_grad_points_vs_direct_derivative(nf, dtype, tile, items):
+    """Point gradient (the window-sum body in its derivative mode, 256 points
+    of an item at a time) against the oracle's derivative sums, at several
+    binning settings."""
     N = (16, 16, 12)
     m = 8 if dtype == "c128" else 4
     fh = rand_coeffs(N, 50)
     x = rand_points(1500, 51)
     r = np.random.default_rng(52)
     G = r.standard_normal(1500) + 1j * r.standard_normal(1500)
-    log(f"grad N={N} m={m} {dtype}")
+    log(f"grad N={N} m={m} tile={tile} items={items} {dtype}")
     p = make_plan(nf, N, m, dtype)
+    p.set_tuning(tile, items)
     p.set_points(to_dev(x))
     got = p.grad_points(to_dev(fh, dtype), to_dev(G, dtype)).cpu().numpy()
     D = oracle.ndft_grad(fh, x)
