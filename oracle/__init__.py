@@ -10,7 +10,7 @@ Two parts:
 * ``ndft_*`` -- plain FP64 direct sums (the definition of the NFFT problem,
   Sec. 2.2.1, evaluated in the one-loop order of eq. (Fs)), in C
   (``oracle/ndft.c``) with POSIX threads, reached through ctypes.  These are
-  the reference every GPU result is judged against.
+  the reference every GPU result is compared with.
 * ``oracle.nfft_steps`` -- a plain numpy FP64 statement of the windowed
   algorithm the GPU implements (deconvolve, oversampled FFT, window sum),
   used to check the GPU stages one at a time.
