@@ -19,7 +19,8 @@ void set_hip_error(hipError_t e, const char *where) {
 }
 
 void allow_lds(const void *kernel, size_t bytes) {
-    if (bytes > 65536) hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    // a failure here shows up as a launch error of the kernel, which is checked
+    if (bytes > 65536) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -142,30 +143,30 @@ bool factor_radices(int n, std::vector<int> &rad) {
 // ---------------------------------------------------------------------------
 
 static void free_points(nfft3_plan_impl *p) {
-    hipFree(p->xs); p->xs = nullptr;
-    hipFree(p->perm); p->perm = nullptr;
-    hipFree(p->bin_of); p->bin_of = nullptr;
-    hipFree(p->rank); p->rank = nullptr;
+    (void)hipFree(p->xs); p->xs = nullptr;
+    (void)hipFree(p->perm); p->perm = nullptr;
+    (void)hipFree(p->bin_of); p->bin_of = nullptr;
+    (void)hipFree(p->rank); p->rank = nullptr;
     p->cap_pts = 0;
 }
 
 static void free_bins(nfft3_plan_impl *p) {
-    hipFree(p->bins.counts); p->bins.counts = nullptr;
-    hipFree(p->bins.offsets); p->bins.offsets = nullptr;
-    hipFree(p->bins.scratch); p->bins.scratch = nullptr;
-    hipFree(p->bins.tile_items); p->bins.tile_items = nullptr;
-    hipFree(p->bins.tile_item_off); p->bins.tile_item_off = nullptr;
+    (void)hipFree(p->bins.counts); p->bins.counts = nullptr;
+    (void)hipFree(p->bins.offsets); p->bins.offsets = nullptr;
+    (void)hipFree(p->bins.scratch); p->bins.scratch = nullptr;
+    (void)hipFree(p->bins.tile_items); p->bins.tile_items = nullptr;
+    (void)hipFree(p->bins.tile_item_off); p->bins.tile_item_off = nullptr;
 }
 static void free_plan(nfft3_plan_impl *p) {
     if (!p) return;
-    hipFree(p->grid);
-    for (void *g : p->extra_grids) hipFree(g);
-    for (int d = 0; d < 3; ++d) { hipFree(p->cdec[d]); hipFree(p->fft[d].tw); hipFree(p->fft[d].stw); }
-    hipFree(p->wcoef);
+    (void)hipFree(p->grid);
+    for (void *g : p->extra_grids) (void)hipFree(g);
+    for (int d = 0; d < 3; ++d) { (void)hipFree(p->cdec[d]); (void)hipFree(p->fft[d].tw); (void)hipFree(p->fft[d].stw); }
+    (void)hipFree(p->wcoef);
     free_points(p);
-    hipFree(p->flag);
+    (void)hipFree(p->flag);
     free_bins(p);
-    hipFree(p->sub.items);
+    (void)hipFree(p->sub.items);
 }
 
 static int validate(const int64_t N[3], double sigma, int m, int dtype, int64_t n[3]) {
@@ -353,7 +354,7 @@ int nfft3_set_stream(nfft3_plan_t p, void *stream) {
 
 int nfft3_destroy(nfft3_plan_t p) {
     if (!p) return NFFT3_OK;
-    if (p->stream) hipStreamSynchronize(p->stream);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
     free_plan(p);
     delete p;
     return NFFT3_OK;
@@ -504,7 +505,7 @@ int nfft3_autotune(nfft3_plan_t p, int64_t M, const double *x, const void *fhat,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     NFFT3_HIP_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return NFFT3_ERR_HIP;
     }
     int best_t = 0, best_i = 0, rc = NFFT3_OK;
@@ -524,7 +525,7 @@ int nfft3_autotune(nfft3_plan_t p, int64_t M, const double *x, const void *fhat,
                     break;
                 }
                 float v = 0.f;
-                hipEventElapsedTime(&v, e0, e1);
+                if (hipEventElapsedTime(&v, e0, e1) != hipSuccess) { rc = NFFT3_ERR_HIP; break; }
                 ms.push_back(v);
             }
             if (rc) break;
@@ -534,8 +535,8 @@ int nfft3_autotune(nfft3_plan_t p, int64_t M, const double *x, const void *fhat,
         }
         if (rc) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     rc = nfft3_set_tuning(p, best_t, best_i);
     if (!rc) rc = nfft3_set_points(p, M, x);

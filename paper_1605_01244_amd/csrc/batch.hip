@@ -214,7 +214,7 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
     if (need > g_batch_cap) {
         if (g_batch_buf) {
             NFFT3_HIP_TRY(hipStreamSynchronize(stream));
-            hipFree(g_batch_buf);
+            (void)hipFree(g_batch_buf);
         }
         g_batch_buf = nullptr;
         g_batch_cap = 0;

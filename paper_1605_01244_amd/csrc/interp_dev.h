@@ -413,7 +413,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
             const uint64_t flexm = __ballot(flex);
             const int need0 = 4 - __popcll(fixed0 & hmask);
             if (flex) {
-                const bool want0 = __popcll(flexm & hmask & below) < need0;
+                const bool want0 = (int)__popcll(flexm & hmask & below) < need0;   // need0 may be < 0
                 if (((u & 1) == 0) != want0) u -= 1;
             }
         }

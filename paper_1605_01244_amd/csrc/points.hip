@@ -252,7 +252,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     NFFT3_HIP_TRY(hipMemcpyAsync(&nitems, p->bins.tile_item_off + ntiles, sizeof(int), hipMemcpyDeviceToHost, s));
     NFFT3_HIP_TRY(hipStreamSynchronize(s));
     if (nitems > p->sub.cap) {
-        hipFree(p->sub.items);
+        (void)hipFree(p->sub.items);
         p->sub.items = nullptr;
         p->sub.cap = 0;
         NFFT3_HIP_TRY(hipMalloc(&p->sub.items, sizeof(int4) * (size_t)std::max(nitems, 1)));
