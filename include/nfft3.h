@@ -70,7 +70,7 @@ enum nfft3_status {
 /* Create a plan for coefficient sizes N[0..2] (host array).
  *   N_d    even, 2 <= N_d (the set I_N of Sec. 2 needs N_d even).
  *   sigma  oversampling factor > 1; n_d = sigma * N_d must be an even integer
- *          whose prime factors are 2, 3 and 5, with n_d <= 2048.
+ *          whose prime factors are 2, 3, 5 and 7, with n_d <= 2048.
  *   m      window half-width in oversampled cells, 1 <= m <= 10, 2m <= n_d.
  *          Typical: m = 4 (about 1e-7 relative error at sigma = 2),
  *          m = 6 (1e-11), m = 8 (1e-14).

@@ -1,6 +1,6 @@
 // Stage (a)+(b) of the windowed evaluation: deconvolution, zero-padding and
 // the 3-D FFT on the oversampled grid, and the transposed pipeline for the
-// adjoint.  Each axis is one pass of self-sorting (Stockham) radix-8/4/2/3/5
+// adjoint.  Each axis is one pass of self-sorting (Stockham) radix-8/4/2/3/5/7
 // FFTs held in LDS:
 //   * the contiguous axis (2) runs lines = rows, loaded with unit stride;
 //   * the strided axes (1, 0) run tiles of C adjacent columns, so every

@@ -92,12 +92,43 @@ __device__ __forceinline__ void dft5(c_t<T> *v) {
     v[3] = csub(p2, q2);
 }
 
+template <typename T, bool FWD>
+__device__ __forceinline__ void dft7(c_t<T> *v) {
+    // pairs a_k = x_k + x_{7-k}, b_k = x_k - x_{7-k}; X_m = x_0 + sum_k cos(2 pi k m/7) a_k
+    // + sgn i sum_k sin(2 pi k m/7) b_k and X_{7-m} the same with - sgn i
+    const T c1 = (T)0.6234898018587335305250048840042398, c2 = (T)-0.2225209339563144042889025644967948,
+            c3 = (T)-0.9009688679024191262361023195074451;
+    const T s1 = (T)0.7818314824680298087084445266740578, s2 = (T)0.9749279121818236070181316829939312,
+            s3 = (T)0.4338837391175581204757683328483588;
+    const c_t<T> a1 = cadd(v[1], v[6]), b1 = csub(v[1], v[6]);
+    const c_t<T> a2 = cadd(v[2], v[5]), b2 = csub(v[2], v[5]);
+    const c_t<T> a3 = cadd(v[3], v[4]), b3 = csub(v[3], v[4]);
+    const c_t<T> x0 = v[0];
+    auto lin3 = [](T p, c_t<T> u, T q, c_t<T> w, T r, c_t<T> z) {
+        return cmk<T>(p * u.x + q * w.x + r * z.x, p * u.y + q * w.y + r * z.y);
+    };
+    const c_t<T> p1 = cadd(x0, lin3(c1, a1, c2, a2, c3, a3));
+    const c_t<T> p2 = cadd(x0, lin3(c2, a1, c3, a2, c1, a3));
+    const c_t<T> p3 = cadd(x0, lin3(c3, a1, c1, a2, c2, a3));
+    const c_t<T> q1 = mul_i<c_t<T>, FWD>(lin3(s1, b1, s2, b2, s3, b3));
+    const c_t<T> q2 = mul_i<c_t<T>, FWD>(lin3(s2, b1, -s3, b2, -s1, b3));
+    const c_t<T> q3 = mul_i<c_t<T>, FWD>(lin3(s3, b1, -s1, b2, s2, b3));
+    v[0] = cadd(x0, cadd(a1, cadd(a2, a3)));
+    v[1] = cadd(p1, q1);
+    v[6] = csub(p1, q1);
+    v[2] = cadd(p2, q2);
+    v[5] = csub(p2, q2);
+    v[3] = cadd(p3, q3);
+    v[4] = csub(p3, q3);
+}
+
 template <typename T, int R, bool FWD>
 __device__ __forceinline__ void dft_small(c_t<T> *v) {
     if constexpr (R == 2) dft2<T, FWD>(v);
     else if constexpr (R == 3) dft3<T, FWD>(v);
     else if constexpr (R == 4) dft4<T, FWD>(v);
     else if constexpr (R == 5) dft5<T, FWD>(v);
+    else if constexpr (R == 7) dft7<T, FWD>(v);
     else dft8<T, FWD>(v);
 }
 
@@ -184,6 +215,7 @@ __device__ __forceinline__ void fft_stage_r(int R, c_t<T> *buf, int ls, int nlin
         case 4: fft_stage<T, 4, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
         case 2: fft_stage<T, 2, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
         case 3: fft_stage<T, 3, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
+        case 7: fft_stage<T, 7, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
         default: fft_stage<T, 5, VMAX, NT, FWD, LINE_FAST, FIRST, LAST>(buf, ls, nlines, n, Ns, tw, ld, st); break;
     }
 }

@@ -61,11 +61,11 @@ struct FftAxisPlan {
     void *stw = nullptr;      // per-stage twiddle tables of the compile-time engine (st_tw_offset)
 };
 
-// Radix plan of a length n = 2^a 3^b 5^c, in application order: radix-8
+// Radix plan of a length n = 2^a 3^b 5^c 7^d, in application order: radix-8
 // stages, then one radix-4 or radix-2 stage for a mod 3 = 2 or 1 (two
 // radix-4 stages instead of 8 x 2 when a mod 3 = 1 and a >= 4), then the
-// radix-3 and the radix-5 stages.  The host's FFT plans and the compile-time
-// engine both use it.
+// radix-3, radix-5 and radix-7 stages.  The host's FFT plans and the
+// compile-time engine both use it.
 constexpr int st_nrad(int n) {
     int a = 0;
     while (n % 2 == 0) { n /= 2; ++a; }
@@ -74,6 +74,7 @@ constexpr int st_nrad(int n) {
     c = q + (r == 4 ? 2 : (r ? 1 : 0));
     while (n % 3 == 0) { n /= 3; ++c; }
     while (n % 5 == 0) { n /= 5; ++c; }
+    while (n % 7 == 0) { n /= 7; ++c; }
     return n == 1 ? c : -1;
 }
 constexpr int st_radix(int n, int s) {
@@ -86,9 +87,10 @@ constexpr int st_radix(int n, int s) {
     if (r == 4) { if (s < 2) return 4; s -= 2; }
     else if (r == 2) { if (s < 1) return 4; s -= 1; }
     else if (r == 1) { if (s < 1) return 2; s -= 1; }
-    int b = 0;
+    int b = 0, c = 0;
     while (n % 3 == 0) { n /= 3; ++b; }
-    return s < b ? 3 : 5;
+    while (n % 5 == 0) { n /= 5; ++c; }
+    return s < b ? 3 : (s < b + c ? 5 : 7);
 }
 // product of the radices before stage s (the Stockham span Ns)
 constexpr int st_ns(int n, int s) {

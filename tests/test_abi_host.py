@@ -51,7 +51,7 @@ def _plan(nf, N=(8, 8, 8), sigma=2.0, m=4, dtype=1):
     ((8, 8, 8), 2.0, 0, 1, -1),      # m < 1
     ((8, 8, 8), 2.0, 9, 1, -1),      # 2m > n
     ((8, 8, 8), 2.0, 11, 1, -1),     # m beyond the supported range
-    ((14, 8, 8), 2.0, 4, 1, -1),     # n = 28 = 4*7: factor 7 unsupported
+    ((22, 8, 8), 2.0, 4, 1, -1),     # n = 44 = 4*11: factor 11 unsupported
     ((8, 8, 8), 2.0, 4, 5, -2),      # bad dtype
     ((2048, 8, 8), 2.0, 4, 1, -1),   # n > 2048
 ])

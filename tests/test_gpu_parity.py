@@ -34,10 +34,11 @@ def make_plan(nf, N, m, dtype, sigma=2.0):
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("N,sigma,m", [((8, 12, 16), 2.0, 3), ((32, 32, 32), 2.0, 6), ((16, 24, 20), 1.5, 4),
                                        ((6, 10, 4), 2.0, 2), ((32, 64, 256), 2.0, 4), ((128, 2, 64), 2.0, 1),
-                                       ((48, 96, 192), 2.0, 4)])
+                                       ((48, 96, 192), 2.0, 4), ((14, 28, 42), 2.0, 4), ((56, 70, 98), 2.0, 5)])
 def test_stage_grid_matches_fft_of_deconvolved(nf, N, sigma, m, dtype):
     """Deconvolve + zero-pad + 3-D FFT equals numpy fftn of the textbook
-    deconvolved array (GPU window normalised: factor phi(0)^3)."""
+    deconvolved array (GPU window normalised: factor phi(0)^3); lengths with
+    factors 2, 3, 5 and 7 (n = 28 ... 196)."""
     log(f"stage_grid N={N} sigma={sigma} m={m} {dtype}")
     fh = rand_coeffs(N, 1)
     p = make_plan(nf, N, m, dtype, sigma)
@@ -292,9 +293,9 @@ def test_folding_and_edges(nf, dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("N,sigma", [((2, 2, 2), 2.0), ((4, 6, 2), 2.0), ((12, 8, 20), 1.5), ((10, 10, 10), 2.0),
-                                     ((64, 4, 8), 2.0)])
+                                     ((64, 4, 8), 2.0), ((14, 28, 6), 2.0), ((16, 32, 8), 1.75)])
 def test_shapes_and_sigma(nf, N, sigma, dtype):
-    """Small, non-cubic, radix-3/5 and sigma = 1.5 grids."""
+    """Small, non-cubic, radix-3/5/7 and sigma = 1.5 / 1.75 grids."""
     m = min(4, min(int(sigma * n) for n in N) // 2)
     fh = rand_coeffs(N, 33)
     x = rand_points(333, 34)

@@ -159,11 +159,13 @@ def _large_case(N):
 
 
 @pytest.mark.parametrize("N,dtype,m", [((512, 512, 512), "c64", 4), ((512, 512, 512), "c128", 8),
-                                       ((500, 250, 120), "c128", 6), ((250, 480, 96), "c64", 4)])
+                                       ((500, 250, 120), "c128", 6), ((250, 480, 96), "c64", 4),
+                                       ((448, 210, 98), "c128", 8)])
 def test_large_and_mixed_radix_sizes(nf, N, dtype, m):
     """The largest single transform (N = 512^3: n = 1024 on the generic FFT
     engine, a 17 GB FP64 grid) and large mixed-radix shapes (n = 1000 / 500 /
-    240 and 500 / 960 / 192, tiles cut by the grid edge): trafo on 40 sampled
+    240, 500 / 960 / 192 and 896 / 420 / 196 with radix-7 stages, tiles cut
+    by the grid edge): trafo on 40 sampled
     points and the adjoint on the 8 corner coefficients against the oracle."""
     import torch
     fhat, x = _large_case(N)
