@@ -88,6 +88,19 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo) and logical CPU count."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs)"
+
+
 def copy_bandwidth(torch, dev, stream, mib=1024, reps=5):
     """Achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB
     (read + write bytes / time, HIP events)."""
@@ -313,7 +326,8 @@ def main():
         cpu = {"value": len(sample) / t_cpu, "unit": "points/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(sample)} seeded points (seed 306) of the 1e7, direct FP64 sum over all "
                          f"{N}^3 coefficients, {t_cpu:.1f} s wall",
-               "single_thread_value": n1 / t1, "single_thread_sample": f"first {n1} points of the sample"}
+               "single_thread_value": n1 / t1, "single_thread_sample": f"first {n1} points of the sample",
+               "cpu_model": cpu_model()}
         for form, r in results.items():
             errs[form] = oracle.rel_errors(r["f_sample"], ref)
         log(f"oracle: {len(sample)} points in {t_cpu:.1f}s on {threads} threads; errors {errs}")
