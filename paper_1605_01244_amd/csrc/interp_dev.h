@@ -240,19 +240,19 @@ __device__ __forceinline__ void ps_store(c_t<T> *buf, const PSItem &it, const in
 // gfx950 serves a 16-byte-per-lane LDS read 16 lanes per clock; two lanes of
 // one 16-lane group conflict when their addresses share a 16-byte bank group
 // (address/16 mod 16).  The stencil is read in 16-byte units: one
-// complex<double>, or an aligned pair of complex<float> (a row of W values is
-// read as W/2+1 pairs, the column weights shifted to the stencil's first
-// element and zero outside it).  At row step j a lane reads stencil row
-// (j + t) mod W; the plane row stride RU (in units) is chosen with
-// W*RU = 0 mod 16, so the bank group of its k-th unit at step j is
-// u + RU*t + RU*j + k mod 16, u being the stencil's first unit.  RU*t runs over
-// the multiples of D = 16/gcd(W, 16) (= gcd(RU, 16)), so each lane picks the
-// rotation t that puts it on a target group of its own within its coset
-// u mod D; with D = 1 (complex<double>, m = 8) every 16-lane group reads
-// conflict-free.  For the complex<float> pairs with D = 2, a stencil starting
-// on an even element can also be read from one unit earlier (weights shifted
-// by two), which flips its coset: those lanes balance the two cosets of each
-// group.  The y weights are rotated with the rows, once per point.
+// complex<double>, or an aligned pair of complex<float>.  complex<float>
+// planes are staged twice, as is (first buffer) and shifted by one element
+// (second buffer, element e at e + 1): a stencil row of W values starting on
+// an even column is W/2 aligned pairs of the first copy, one starting on an
+// odd column W/2 aligned pairs of the second, so no read carries a value
+// outside the stencil.  At row step j a lane reads stencil row (j + t) mod W;
+// the plane row stride RU (in units) is chosen with W*RU = 0 mod 16, so the
+// bank group of its k-th unit at step j is u + RU*t + RU*j + k mod 16, u being
+// the stencil's first unit.  RU*t runs over the multiples of
+// D = 16/gcd(W, 16) (= gcd(RU, 16)), so each lane picks the rotation t that
+// puts it on a target group of its own within its coset u mod D; with D = 1
+// (complex<double>, m = 8) every 16-lane group reads conflict-free.  The y
+// weights are rotated with the rows, once per point.
 
 template <typename T> struct LdsUnit;
 template <> struct LdsUnit<double> {
@@ -336,7 +336,8 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
     constexpr int m = W / 2;
     using U = typename LdsUnit<T>::type;
     constexpr int EPU = LdsUnit<T>::EPU;
-    constexpr int NR = EPU == 1 ? W : W / 2 + 1;   // units read per stencil row
+    constexpr bool TWIN = EPU == 2;                // complex<float>: aligned + shifted copy
+    constexpr int NR = EPU == 1 ? W : W / 2;       // units read per stencil row
     constexpr int NW = NR * EPU;                   // column weights per row
     constexpr int D = 16 / cgcd(W, 16);            // cosets of bank groups
     constexpr int NT = 16 / D;                     // distinct rotations
@@ -354,13 +355,6 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
     for (int i = threadIdx.x; i < W * zrow; i += kPsThreads) {
         const int r = i / zrow, q = i - r * zrow;
         scoef[i] = q <= a.deg ? coef[r * (a.deg + 1) + q] : (T)0;
-    }
-    // the pad columns are read (with zero weight) by the pair layout: clear
-    // them once; staging never writes them
-    const int npad = it.PXp - it.PX;
-    for (int e = threadIdx.x; e < 2 * it.PY * npad; e += kPsThreads) {
-        const int r = e / npad, col = it.PX + (e - r * npad);
-        buf0[r * it.PXp + col] = cmk<T>(0, 0);     // rows 0 .. 2 PY - 1 span both buffers
     }
 
     const int lane = threadIdx.x & 63;
@@ -404,44 +398,23 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
                 window_weights<T, W>(f2, coef, a.deg, w2);
             }
         }
-        int u = s / EPU;
-        if constexpr (EPU == 2 && D == 2) {
-            // even starts (s >= 2, so the earlier unit exists) may take either
-            // coset; they balance the cosets within each 8-lane half
-            const bool flex = active && !(s & 1) && s >= 2;
-            const uint64_t fixed0 = __ballot(active && !flex && !(u & 1));
-            const uint64_t flexm = __ballot(flex);
-            const int need0 = 4 - __popcll(fixed0 & hmask);
-            if (flex) {
-                const bool want0 = (int)__popcll(flexm & hmask & below) < need0;   // need0 may be < 0
-                if (((u & 1) == 0) != want0) u -= 1;
-            }
-        }
-        const int sh = s - u * EPU;            // stencil offset in the read window: 0, 1 or 2
+        // first unit of the stencil row: complex<double> at s; complex<float>
+        // with an even first column in the first copy (buf0) at s/2, with an
+        // odd one in the shifted copy (buf1, element e at e + 1), (bufsz + s + 1)/2
+        // units from buf0
+        const int u = TWIN ? ((s & 1) ? (bufsz + s + 1) / 2 : s / 2) : s;
 #pragma unroll
         for (int c = 0; c < NW; ++c) {
-            T v = (c < W) ? w2[c] : (T)0;
-            if (EPU == 2) {
-                const T v1 = (c >= 1 && c - 1 < W) ? w2[c - 1] : (T)0;
-                const T v2 = (c >= 2 && c - 2 < W) ? w2[c - 2] : (T)0;
-                v = sh == 0 ? v : (sh == 1 ? v1 : v2);
-            }
-            wt[k][c] = v;
-            if constexpr (GRAD) {
-                T q = (c < W) ? e2[c] : (T)0;
-                if (EPU == 2) {
-                    const T q1 = (c >= 1 && c - 1 < W) ? e2[c - 1] : (T)0;
-                    const T q2 = (c >= 2 && c - 2 < W) ? e2[c - 2] : (T)0;
-                    q = sh == 0 ? q : (sh == 1 ? q1 : q2);
-                }
-                dt[k][c] = q;
-            }
+            wt[k][c] = w2[c];
+            if constexpr (GRAD) dt[k][c] = e2[c];
         }
         // rank within the lane's coset and 16-lane group -> target bank group.
         // Two cosets: ranks are taken per 8-lane half and the halves get
         // disjoint target ranges (cs + 2 {0..3} and cs + 8 + 2 {0..3}), so the
         // targets are distinct within each half as well as within the group
         // (measured 2% faster than group-wide ranks for complex<float>, m = 4).
+        // A coset holding more than 4 lanes of a half shares targets: the
+        // cosets follow the stencils' columns and are not balanced.
         const int cs = u & (D - 1);
         int rank = 0;
 #pragma unroll
@@ -479,6 +452,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
     } else {
         ps_fetch<T, NF>(grid, off, (int64_t)wrapi(it.zbeg + (down ? np - 1 : 0), a.n0) * plane, stage);
         ps_store<T, NF>(buf0, it, lidx, stage);
+        if constexpr (TWIN) ps_store<T, NF>(buf1 + 1, it, lidx, stage);
     }
     __syncthreads();
 
@@ -493,7 +467,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
             else
                 ps_fetch<T, NF>(grid, off, zoff, stage);
         }
-        const U *pl = reinterpret_cast<const U *>((st & 1) ? buf1 : buf0);
+        const U *pl = reinterpret_cast<const U *>(TWIN ? buf0 : ((st & 1) ? buf1 : buf0));
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int r0 = i - zlo[k];
@@ -588,6 +562,12 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
         }
         if constexpr (kDirect) {
             __builtin_amdgcn_s_waitcnt(0);
+        } else if constexpr (TWIN) {
+            __syncthreads();      // every read of this plane is done
+            if (more) {
+                ps_store<T, NF>(buf0, it, lidx, stage);
+                ps_store<T, NF>(buf1 + 1, it, lidx, stage);
+            }
         } else {
             if (more) ps_store<T, NF>((st & 1) ? buf0 : buf1, it, lidx, stage);
         }
@@ -639,8 +619,8 @@ inline PSArgs ps_args(const nfft3_plan_impl *p) {
     return a;
 }
 
-// Row stride of the interp kernel's staged planes: at least PX (+2 elements
-// read past the stencil by the complex<float> pair layout), a whole number RU
+// Row stride of the interp kernel's staged planes: at least PX (+2 for
+// complex<float>, whose shifted copy holds element PX - 1 at PX), a whole number RU
 // of 16-byte units with gcd(RU mod 16, 16) = D = 16/gcd(W, 16); and the
 // inverse of RU/D modulo 16/D.
 inline void interp_layout(const nfft3_plan_impl *p, PSArgs &a) {
