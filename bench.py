@@ -43,12 +43,27 @@ TRAFFIC_SOURCES = ["paper_1605_01244_amd/csrc/interp_dev.h", "paper_1605_01244_a
 TRAFFIC_PROFILE = "profiles/interp_window_sums_N256_M1e7_traffic.md"
 
 
-def kernel_sources_sha():
+def strip_comments(src: str) -> str:
+    """C++ source without comments and with whitespace collapsed (the code
+    the counters depend on)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_sources_sha(read=None):
+    """Hash of the window-sum kernel sources, comments and layout ignored.
+    `read(path)` returns a file's text (default: the working tree)."""
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fp:
-            h.update(fp.read())
+        if read is None:
+            with open(os.path.join(ROOT, f)) as fp:
+                text = fp.read()
+        else:
+            text = read(f)
+        h.update(strip_comments(text).encode())
     return h.hexdigest()
 
 

@@ -7,12 +7,15 @@
 // fraction are formed in FP64 in both precisions.
 //
 // Plane streaming.  Points are sorted by (tile, z-cell), a tile being a
-// By x Bx block of (y, x) cells; a work item is at most 256 points of one tile
-// column (one point per thread).  The workgroup walks the grid planes
+// By x Bx block of (y, x) cells; a work item is at most 512 points (two per
+// thread of a 256-thread workgroup; 256 through nfft3_set_tuning) of one tile
+// column spanning at most 64 z-cells.  The workgroup walks the grid planes
 // z = zmin-m+1 .. zmax+m of its item; each plane's (By+2m-1) x (Bx+2m-1)
 // region (the tile plus the stencil halo, wrapped periodically) is staged in
-// LDS, double-buffered, with the next plane's global loads issued into
-// registers before the current plane is consumed.  A thread whose point has
+// LDS, with the next plane's global loads issued before the current plane is
+// consumed: complex<double> double-buffered (m = 8 by direct global-to-LDS
+// loads), complex<float> as two copies (as is and shifted by one element) in
+// one buffer.  A thread whose point has
 // the plane inside its stencil adds w0 * sum_{r1,r2} w1 w2 g from LDS; the y/x
 // weights live in registers for the whole item, the z weight is one polynomial
 // per plane.  The spread kernel accumulates each plane in LDS with LDS atomics
