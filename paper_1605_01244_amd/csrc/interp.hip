@@ -51,15 +51,31 @@ grad_ps_kernel(PSArgs a) {
 // LDS float atomic add runs ~15x slower than an LDS 64-bit integer atomic
 // add (measured), whatever the address pattern.  A chunk of at most 512
 // points (PPT per thread; slot k of thread t is sorted index lo + k 256 + t)
-// is accumulated at scale 2^k, k = 52 - e with max|f| < 2^e, so every
-// contribution |f w0 w1 w2| 2^k (window values <= 1) is below 2^52 and any
-// sum of at most 512 of them stays below 2^61; a contribution is rounded to
-// the nearest integer, an error of at most 2^(e-53) <= 2^-52 max|f| (one FP64
-// ulp of the chunk's largest value).  Each plane is flushed once per chunk: converted back
-// (exact power-of-two scaling) and added to the grid with global atomics,
-// whose rate bounds the complex<float> form, hence two points per thread
-// there (one walk and one flush per 512-point item).
-__device__ __forceinline__ long long fixed_round(double x) { return __double2ll_rn(x); }
+// is accumulated at scale 2^k, k = 53 - e with max|f| < 2^e, so every
+// contribution |f w0 w1 w2| 2^k (window values <= 1) is below 2^53 and any
+// sum of at most 512 of them stays below 2^62.  A contribution p = a b is
+// rounded to the nearest integer by three fused multiply-adds and integer
+// adds, without conversion instructions.  With C = 1.5 2^52 the doubles in
+// [2^52, 2^53] are the integers and adjacent doubles have adjacent bit
+// patterns, so y = fma(a, b/4, C) holds q1 = rint(p/4) as bits(y) - bits(C)
+// (|p/4| < 2^51; C's low word is zero, so only the high word is adjusted);
+// fma(y, -4, 5C) = C - 4 q1 exactly; z = fma(a, b, C - 4 q1) holds
+// rint(p - 4 q1), |.| <= 2, in its low word; and rint(p) = 4 q1 +
+// rint(p - 4 q1), with one rounding of the exact product.  The error is at
+// most 2^(e-54), half an FP64 ulp of the chunk's largest value (2^-53 max|f|
+// up to the 1.0001 margin on the scale).  Each plane is flushed once per
+// chunk: converted back (exact power-of-two scaling) and added to the grid
+// with global atomics, whose rate bounds the complex<float> form, hence two
+// points per thread there (one walk and one flush per 512-point item).
+__device__ __forceinline__ unsigned long long fixed_fma(double a, double b4, double b) {
+    constexpr double C = 6755399441055744.0;          // 1.5 2^52
+    const double y = __fma_rn(a, b4, C);              // C + q1, q1 = rint(a b / 4)
+    const double t = __fma_rn(y, -4.0, 5.0 * C);      // C - 4 q1 (exact)
+    const double z = __fma_rn(a, b, t);               // C + rint(a b - 4 q1), |.| <= 2
+    const unsigned hi = (unsigned)__double2hiint(y) - 0x43380000u;
+    const unsigned long long q1 = ((unsigned long long)hi << 32) | (unsigned)__double2loint(y);
+    return (q1 << 2) + (unsigned long long)(long long)__double2loint(z);
+}
 
 template <typename T, int W, int PPT>
 __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
@@ -106,7 +122,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
             amax = fmaxf(amax, (float)fmax(fabs((double)v[k].x), fabs((double)v[k].y)));
         }
     }
-    // chunk scale 2^ks: 2^ks max|f| < 2^52
+    // chunk scale 2^ks: 2^ks max|f| < 2^53
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
     constexpr int NF = ps_nf<W>();
@@ -120,7 +136,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     for (int w = 0; w < kPsThreads / 64; ++w) bmax = fmaxf(bmax, wmax[w]);
     int ex = 0;
     if (bmax > 0.f) frexpf(bmax * 1.0001f, &ex);   // bmax < 2^ex (float rounding of |f| covered)
-    const int ks = 52 - ex;
+    const int ks = 53 - ex;
     double vr0[PPT], vi0[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -138,11 +154,12 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
                 for (int r1 = 0; r1 < W; ++r1) {
                     unsigned long long *row = acc + base[k] + 2 * r1 * it.PX;
                     const double br = (double)w1[k][r1] * vr, bi = (double)w1[k][r1] * vi;
+                    const double br4 = 0.25 * br, bi4 = 0.25 * bi;
 #pragma unroll
                     for (int r2 = 0; r2 < W; ++r2) {
                         const double w2d = (double)w2[k][r2];
-                        atomicAdd(&row[2 * r2], (unsigned long long)fixed_round(w2d * br));
-                        atomicAdd(&row[2 * r2 + 1], (unsigned long long)fixed_round(w2d * bi));
+                        atomicAdd(&row[2 * r2], fixed_fma(w2d, br4, br));
+                        atomicAdd(&row[2 * r2 + 1], fixed_fma(w2d, bi4, bi));
                     }
                 }
             }

@@ -70,6 +70,7 @@ def test_stage_interp_matches_window_sum(nf, N, m, M, dtype):
     got = p.stage_interp().cpu().numpy()
     ref = ns.interpolate(g, x, m, 2.0) / phi0(m, 2.0) ** 3
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.3g} rel-linf {li:.3g}")
     assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
 
 
@@ -113,6 +114,7 @@ def test_stage_interp_tunings(nf, tile, items, dtype):
     got = p.stage_interp().cpu().numpy()
     ref = ns.interpolate(g, x, m, 2.0) / phi0(m, 2.0) ** 3
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.3g} rel-linf {li:.3g}")
     assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
 
 
@@ -149,6 +151,7 @@ def test_stage_spread_matches_numpy(nf, dtype):
     got = p.grid().cpu().numpy()
     ref = ns.spread(f, x, p.n, m, 2.0) / phi0(m, 2.0) ** 3
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.3g} rel-linf {li:.3g}")
     assert l2 < (1e-14 if dtype == "c128" else 1e-6), (l2, li)
 
 
@@ -173,6 +176,7 @@ def test_stage_spread_every_m_and_items(nf, m, tile, items, dtype):
     got = p.grid().cpu().numpy()
     ref = ns.spread(f, x, p.n, m, 2.0) / phi0(m, 2.0) ** 3
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.3g} rel-linf {li:.3g}")
     assert l2 < stage_tol(m, dtype), (l2, li)
 
 
@@ -193,6 +197,7 @@ def test_stage_spread_pileup_and_dynamic_range(nf, dtype):
     got = p.grid().cpu().numpy()
     ref = ns.spread(f, x, p.n, m, 2.0) / phi0(m, 2.0) ** 3
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.3g} rel-linf {li:.3g}")
     assert l2 < stage_tol(m, dtype), (l2, li)
 
 
