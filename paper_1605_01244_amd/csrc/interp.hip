@@ -65,8 +65,9 @@ grad_ps_kernel(PSArgs a) {
 // most 2^(e-54), half an FP64 ulp of the chunk's largest value (2^-53 max|f|
 // up to the 1.0001 margin on the scale).  Each plane is flushed once per
 // chunk: converted back (exact power-of-two scaling) and added to the grid
-// with global atomics, whose rate bounds the complex<float> form, hence two
-// points per thread there (one walk and one flush per 512-point item).
+// with global atomics, whose rate bounds the kernel when a 512-point item is
+// taken in two chunks, hence two points per thread (one walk and one flush
+// per item) where the registers allow.
 __device__ __forceinline__ unsigned long long fixed_fma(double a, double b4, double b) {
     constexpr double C = 6755399441055744.0;          // 1.5 2^52
     const double y = __fma_rn(a, b4, C);              // C + q1, q1 = rint(a b / 4)
@@ -94,9 +95,19 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
     for (int e = threadIdx.x; e < 2 * it.psz; e += kPsThreads) acc[e] = 0ull;
 
+    // W = 16: lane l of each 16-lane group walks its stencil rows starting at
+    // row t, chosen so that all its atomics fall in bank group l mod 16
+    // offset by a step-dependent constant.  Element e's 16-byte bank group is
+    // e mod 16; at step (j, r2) a lane adds to element c + ((j + t) mod 16) PX
+    // + r2 (c its stencil's first element), which is c + t PX + j PX + r2 mod
+    // 16; the region's row length PX = B + 2m - 1 is odd, hence invertible
+    // mod 16, and t = (l - c) PX^-1 mod 16 makes c + t PX = l.  The row
+    // weights are rotated with the rows, once per point.
+    constexpr bool ROT = W == 16;
+    const int pxinv = (it.PX * (2 - it.PX * it.PX)) & 15;   // PX^-1 mod 16
     T w1[PPT][W], w2[PPT][W];
     T f0[PPT];
-    int zlo[PPT], base[PPT];
+    int zlo[PPT], base[PPT], rot[PPT];
     c_t<T> v[PPT];
     float amax = 0.f;
 #pragma unroll
@@ -105,6 +116,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         f0[k] = 0;
         zlo[k] = -4 * W;     // never active
         base[k] = 0;
+        rot[k] = 0;
         v[k] = cmk<T>(0, 0);
 #pragma unroll
         for (int r = 0; r < W; ++r) { w1[k][r] = 0; w2[k][r] = 0; }
@@ -118,6 +130,10 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
             base[k] = 2 * ((yc - it.y0) * it.PX + (xc - it.x0));
             window_weights<T, W>(f1, coef, a.deg, w1[k]);
             window_weights<T, W>(f2, coef, a.deg, w2[k]);
+            if constexpr (ROT) {
+                rot[k] = (((int)(threadIdx.x & 15) - (base[k] >> 1)) * pxinv) & 15;
+                rotate_rows<T, W, 16>(w1[k], rot[k]);
+            }
             v[k] = ((const c_t<T> *)a.vals)[a.perm[pk]];
             amax = fmaxf(amax, (float)fmax(fabs((double)v[k].x), fabs((double)v[k].y)));
         }
@@ -152,7 +168,8 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
                 const double w0 = (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
                 const double vr = w0 * vr0[k], vi = w0 * vi0[k];
                 for (int r1 = 0; r1 < W; ++r1) {
-                    unsigned long long *row = acc + base[k] + 2 * r1 * it.PX;
+                    const int rr = ROT ? (r1 + rot[k]) & 15 : r1;
+                    unsigned long long *row = acc + base[k] + 2 * rr * it.PX;
                     const double br = (double)w1[k][r1] * vr, bi = (double)w1[k][r1] * vi;
                     const double br4 = 0.25 * br, bi4 = 0.25 * bi;
 #pragma unroll
@@ -233,9 +250,11 @@ static int spread_w(nfft3_plan_impl *p, const void *f, void *grid) {
     // 16 bytes (two 64-bit fixed-point values) per staged element + the coefficients
     const size_t psz = (size_t)(p->bins.By + W - 1) * (p->bins.Bx + W - 1);
     const size_t lds = psz * 16 + (size_t)W * (p->deg + 1) * sizeof(T);
-    // complex<float> up to m = 4: two points per thread (flush-bound);
-    // otherwise one (registers; complex<double> is bound by the LDS atomics)
-    constexpr int PPT = sizeof(T) == 4 && W <= 8 ? 2 : 1;
+    // Two points per thread (complex<float> up to m = 4, complex<double> up
+    // to m = 8): a 512-point item is walked and flushed once, not twice; the
+    // global-atomic flush of every plane otherwise bounds the kernel.  Wider
+    // complex<float> stencils keep one (registers).
+    constexpr int PPT = (sizeof(T) == 4 ? W <= 8 : W <= 16) ? 2 : 1;
     allow_lds((const void *)spread_ps_kernel<T, W, PPT>, lds);
     hipLaunchKernelGGL((spread_ps_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
                        p->stream, a);
