@@ -210,10 +210,11 @@ int launch_grid_forward(nfft3_plan_impl *p, const void *fhat, void *grid, int de
 int launch_grid_adjoint(nfft3_plan_impl *p, void *grid, void *fhat);
 // points (points.hip)
 int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x);
-// window sums (interp.hip)
+// window sums and their point derivative (interp.hip)
 int launch_interp(nfft3_plan_impl *p, const void *grid, void *f);
-int launch_spread(nfft3_plan_impl *p, const void *f, void *grid);
 int launch_grad(nfft3_plan_impl *p, const void *grid, const void *G, double *grad_x);
+// spreading, the adjoint window step, and the grid fill (spread.hip)
+int launch_spread(nfft3_plan_impl *p, const void *f, void *grid);
 int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);
 // batch (batch.hip)
 int launch_batch(int T, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out,

@@ -1,7 +1,7 @@
-// Stage (c) of the windowed evaluation and its transposes:
+// Stage (c) of the windowed evaluation and its derivative in the points:
 //   interp : f_j      = sum_{r in {-m+1..m}^3} g[(u_j + r) mod n] prod_d w_d(r_d)
-//   spread : g[u_j+r] += f_j prod_d w_d(r_d)                      (adjoint)
 //   grad   : d f_j/d x_{j,d} = n_d sum_r g[...] w_d'(r_d) prod_{e != d} w_e(r_e)
+// (the adjoint, spreading, is in spread.hip)
 // with u_j = floor(n x_j) and w_d(r) = phi((n x_j)_d - u_d - r)/phi(0) from the
 // per-offset window polynomials in the cell fraction (see api.hip).  Cell and
 // fraction are formed in FP64 in both precisions.
@@ -18,9 +18,7 @@
 // one buffer.  A thread whose point has
 // the plane inside its stencil adds w0 * sum_{r1,r2} w1 w2 g from LDS; the y/x
 // weights live in registers for the whole item, the z weight is one polynomial
-// per plane.  The spread kernel accumulates each plane in LDS with LDS atomics
-// (64-bit fixed point, see spread_ps_kernel) and flushes it to the grid with
-// global atomics.
+// per plane.  The spread kernel (spread.hip) walks the same items and planes.
 #include "interp_dev.h"
 
 namespace nfft3 {
@@ -44,176 +42,6 @@ grad_ps_kernel(PSArgs a) {
         __syncthreads();
         interp_range<T, W, 1, true>(a, idx, make_int4(item.x, lo, min(item.z, lo + kPsThreads), 0), smem_raw);
     }
-}
-
-// ------------------------------------------------------------ spread ----
-// The plane accumulator in LDS holds 64-bit fixed-point values: on gfx950 an
-// LDS float atomic add runs ~15x slower than an LDS 64-bit integer atomic
-// add (measured), whatever the address pattern.  A chunk of at most 512
-// points (PPT per thread; slot k of thread t is sorted index lo + k 256 + t)
-// is accumulated at scale 2^k, k = 53 - e with max|f| < 2^e, so every
-// contribution |f w0 w1 w2| 2^k (window values <= 1) is below 2^53 and any
-// sum of at most 512 of them stays below 2^62.  A contribution p = a b is
-// rounded to the nearest integer by three fused multiply-adds and integer
-// adds, without conversion instructions.  With C = 1.5 2^52 the doubles in
-// [2^52, 2^53] are the integers and adjacent doubles have adjacent bit
-// patterns, so y = fma(a, b/4, C) holds q1 = rint(p/4) as bits(y) - bits(C)
-// (|p/4| < 2^51; C's low word is zero, so only the high word is adjusted);
-// fma(y, -4, 5C) = C - 4 q1 exactly; z = fma(a, b, C - 4 q1) holds
-// rint(p - 4 q1), |.| <= 2, in its low word; and rint(p) = 4 q1 +
-// rint(p - 4 q1), with one rounding of the exact product.  The error is at
-// most 2^(e-54), half an FP64 ulp of the chunk's largest value (2^-53 max|f|
-// up to the 1.0001 margin on the scale).  Each plane is flushed once per
-// chunk: converted back (exact power-of-two scaling) and added to the grid
-// with global atomics, whose rate bounds the kernel when a 512-point item is
-// taken in two chunks, hence two points per thread (one walk and one flush
-// per item) where the registers allow.
-__device__ __forceinline__ unsigned long long fixed_fma(double a, double b4, double b) {
-    constexpr double C = 6755399441055744.0;          // 1.5 2^52
-    const double y = __fma_rn(a, b4, C);              // C + q1, q1 = rint(a b / 4)
-    const double t = __fma_rn(y, -4.0, 5.0 * C);      // C - 4 q1 (exact)
-    const double z = __fma_rn(a, b, t);               // C + rint(a b - 4 q1), |.| <= 2
-    const unsigned hi = (unsigned)__double2hiint(y) - 0x43380000u;
-    const unsigned long long q1 = ((unsigned long long)hi << 32) | (unsigned)__double2loint(y);
-    return (q1 << 2) + (unsigned long long)(long long)__double2loint(z);
-}
-
-template <typename T, int W, int PPT>
-__global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
-    constexpr int m = W / 2;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ float wmax[kPsThreads / 64];
-    const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
-    for (int lo = item.y; lo < item.z; lo += kPsThreads * PPT) {
-    __syncthreads();
-    const int hi = min(item.z, lo + kPsThreads * PPT);
-    const PSItem it = ps_range(a, m, item.x, lo, hi);
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);   // (re, im) per element
-    T *scoef = reinterpret_cast<T *>(acc + 2 * it.psz);
-    const T *coef = (const T *)a.coef;
-    const int nc = W * (a.deg + 1);
-    for (int i = threadIdx.x; i < nc; i += kPsThreads) scoef[i] = coef[i];
-    for (int e = threadIdx.x; e < 2 * it.psz; e += kPsThreads) acc[e] = 0ull;
-
-    // W = 16: lane l of each 16-lane group walks its stencil rows starting at
-    // row t, chosen so that all its atomics fall in bank group l mod 16
-    // offset by a step-dependent constant.  Element e's 16-byte bank group is
-    // e mod 16; at step (j, r2) a lane adds to element c + ((j + t) mod 16) PX
-    // + r2 (c its stencil's first element), which is c + t PX + j PX + r2 mod
-    // 16; the region's row length PX = B + 2m - 1 is odd, hence invertible
-    // mod 16, and t = (l - c) PX^-1 mod 16 makes c + t PX = l.  The row
-    // weights are rotated with the rows, once per point.
-    constexpr bool ROT = W == 16;
-    const int pxinv = (it.PX * (2 - it.PX * it.PX)) & 15;   // PX^-1 mod 16
-    T w1[PPT][W], w2[PPT][W];
-    T f0[PPT];
-    int zlo[PPT], base[PPT], rot[PPT];
-    c_t<T> v[PPT];
-    float amax = 0.f;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int pk = lo + k * kPsThreads + threadIdx.x;
-        f0[k] = 0;
-        zlo[k] = -4 * W;     // never active
-        base[k] = 0;
-        rot[k] = 0;
-        v[k] = cmk<T>(0, 0);
-#pragma unroll
-        for (int r = 0; r < W; ++r) { w1[k][r] = 0; w2[k][r] = 0; }
-        if (pk < hi) {
-            const double *xp = a.xs + 3 * pk;
-            T f1, f2;
-            const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
-            const int yc = cell_frac<T>(xp[1], a.n1, f1);
-            const int xc = cell_frac<T>(xp[2], a.n2, f2);
-            zlo[k] = zc - m + 1 - it.zbeg;
-            base[k] = 2 * ((yc - it.y0) * it.PX + (xc - it.x0));
-            window_weights<T, W>(f1, coef, a.deg, w1[k]);
-            window_weights<T, W>(f2, coef, a.deg, w2[k]);
-            if constexpr (ROT) {
-                rot[k] = (((int)(threadIdx.x & 15) - (base[k] >> 1)) * pxinv) & 15;
-                rotate_rows<T, W, 16>(w1[k], rot[k]);
-            }
-            v[k] = ((const c_t<T> *)a.vals)[a.perm[pk]];
-            amax = fmaxf(amax, (float)fmax(fabs((double)v[k].x), fabs((double)v[k].y)));
-        }
-    }
-    // chunk scale 2^ks: 2^ks max|f| < 2^53
-    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
-    constexpr int NF = ps_nf<W>();
-    int off[NF], lidx[NF];
-    ps_offsets<NF>(a, it, m, off, lidx);
-    c_t<T> *grid = (c_t<T> *)a.grid_out;
-    const int64_t plane = (int64_t)a.n1 * a.n2;
-    __syncthreads();
-    float bmax = 0.f;
-#pragma unroll
-    for (int w = 0; w < kPsThreads / 64; ++w) bmax = fmaxf(bmax, wmax[w]);
-    int ex = 0;
-    if (bmax > 0.f) frexpf(bmax * 1.0001f, &ex);   // bmax < 2^ex (float rounding of |f| covered)
-    const int ks = 53 - ex;
-    double vr0[PPT], vi0[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        vr0[k] = ldexp((double)v[k].x, ks);
-        vi0[k] = ldexp((double)v[k].y, ks);
-    }
-
-    for (int i = 0; i < it.nplanes; ++i) {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int r0 = i - zlo[k];
-            if (r0 >= 0 && r0 < W) {
-                const double w0 = (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
-                const double vr = w0 * vr0[k], vi = w0 * vi0[k];
-                for (int r1 = 0; r1 < W; ++r1) {
-                    const int rr = ROT ? (r1 + rot[k]) & 15 : r1;
-                    unsigned long long *row = acc + base[k] + 2 * rr * it.PX;
-                    const double br = (double)w1[k][r1] * vr, bi = (double)w1[k][r1] * vi;
-                    const double br4 = 0.25 * br, bi4 = 0.25 * bi;
-#pragma unroll
-                    for (int r2 = 0; r2 < W; ++r2) {
-                        const double w2d = (double)w2[k][r2];
-                        atomicAdd(&row[2 * r2], fixed_fma(w2d, br4, br));
-                        atomicAdd(&row[2 * r2 + 1], fixed_fma(w2d, bi4, bi));
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // flush this plane to the grid and clear it
-        const int64_t zoff = (int64_t)wrapi(it.zbeg + i, a.n0) * plane;
-#pragma unroll
-        for (int kk = 0; kk < NF; ++kk) {
-            const int e = threadIdx.x + kk * kPsThreads;
-            if (e < it.psz) {
-                const long long sr = (long long)acc[2 * e], si = (long long)acc[2 * e + 1];
-                if (sr != 0 || si != 0) {
-                    unsafeAtomicAdd(&grid[zoff + off[kk]].x, (T)ldexp((double)sr, -ks));
-                    unsafeAtomicAdd(&grid[zoff + off[kk]].y, (T)ldexp((double)si, -ks));
-                    acc[2 * e] = 0ull;
-                    acc[2 * e + 1] = 0ull;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    }
-}
-
-__global__ void zero_kernel(float4 *p, int64_t count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
-int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes) {
-    const int64_t count = (int64_t)(bytes / 16);
-    if (count == 0) return NFFT3_OK;
-    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, p->stream,
-                       (float4 *)buf, count);
-    NFFT3_LAUNCH_CHECK("zero_kernel");
-    return NFFT3_OK;
 }
 
 // ------------------------------------------------------------ dispatch ----
@@ -242,27 +70,6 @@ static int interp_w(nfft3_plan_impl *p, const void *grid, void *f) {
 }
 
 template <typename T, int W>
-static int spread_w(nfft3_plan_impl *p, const void *f, void *grid) {
-    if (p->M == 0 || p->sub.count == 0) return NFFT3_OK;
-    PSArgs a = ps_args(p);
-    a.vals = f;
-    a.grid_out = grid;
-    // 16 bytes (two 64-bit fixed-point values) per staged element + the coefficients
-    const size_t psz = (size_t)(p->bins.By + W - 1) * (p->bins.Bx + W - 1);
-    const size_t lds = psz * 16 + (size_t)W * (p->deg + 1) * sizeof(T);
-    // Two points per thread (complex<float> up to m = 4, complex<double> up
-    // to m = 8): a 512-point item is walked and flushed once, not twice; the
-    // global-atomic flush of every plane otherwise bounds the kernel.  Wider
-    // complex<float> stencils keep one (registers).
-    constexpr int PPT = (sizeof(T) == 4 ? W <= 8 : W <= 16) ? 2 : 1;
-    allow_lds((const void *)spread_ps_kernel<T, W, PPT>, lds);
-    hipLaunchKernelGGL((spread_ps_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
-                       p->stream, a);
-    NFFT3_LAUNCH_CHECK("spread_ps_kernel");
-    return NFFT3_OK;
-}
-
-template <typename T, int W>
 static int grad_w(nfft3_plan_impl *p, const void *grid, const void *G, double *gx) {
     if (p->M == 0 || p->sub.count == 0) return NFFT3_OK;
     PSArgs a = interp_args(p);
@@ -277,29 +84,9 @@ static int grad_w(nfft3_plan_impl *p, const void *grid, const void *G, double *g
     return NFFT3_OK;
 }
 
-#define NFFT3_DISPATCH_M(FN, T, ...)                     \
-    switch (p->m) {                                      \
-        case 1: return FN<T, 2>(p, __VA_ARGS__);         \
-        case 2: return FN<T, 4>(p, __VA_ARGS__);         \
-        case 3: return FN<T, 6>(p, __VA_ARGS__);         \
-        case 4: return FN<T, 8>(p, __VA_ARGS__);         \
-        case 5: return FN<T, 10>(p, __VA_ARGS__);        \
-        case 6: return FN<T, 12>(p, __VA_ARGS__);        \
-        case 7: return FN<T, 14>(p, __VA_ARGS__);        \
-        case 8: return FN<T, 16>(p, __VA_ARGS__);        \
-        case 9: return FN<T, 18>(p, __VA_ARGS__);        \
-        case 10: return FN<T, 20>(p, __VA_ARGS__);       \
-        default: return NFFT3_ERR_INVALID_ARG;           \
-    }
-
 int launch_interp(nfft3_plan_impl *p, const void *grid, void *f) {
     if (p->dtype == NFFT3_C128) { NFFT3_DISPATCH_M(interp_w, double, grid, f) }
     NFFT3_DISPATCH_M(interp_w, float, grid, f)
-}
-
-int launch_spread(nfft3_plan_impl *p, const void *f, void *grid) {
-    if (p->dtype == NFFT3_C128) { NFFT3_DISPATCH_M(spread_w, double, f, grid) }
-    NFFT3_DISPATCH_M(spread_w, float, f, grid)
 }
 
 int launch_grad(nfft3_plan_impl *p, const void *grid, const void *G, double *gx) {

@@ -671,4 +671,20 @@ inline size_t ps_lds(const nfft3_plan_impl *p, int nbuf) {
     return nbuf * psz * p->elt + (size_t)W * (p->deg + 1) * (p->elt / 2);
 }
 
+// Dispatch on the half-width m to the stencil-width template W = 2m.
+#define NFFT3_DISPATCH_M(FN, T, ...)                     \
+    switch (p->m) {                                      \
+        case 1: return FN<T, 2>(p, __VA_ARGS__);         \
+        case 2: return FN<T, 4>(p, __VA_ARGS__);         \
+        case 3: return FN<T, 6>(p, __VA_ARGS__);         \
+        case 4: return FN<T, 8>(p, __VA_ARGS__);         \
+        case 5: return FN<T, 10>(p, __VA_ARGS__);        \
+        case 6: return FN<T, 12>(p, __VA_ARGS__);        \
+        case 7: return FN<T, 14>(p, __VA_ARGS__);        \
+        case 8: return FN<T, 16>(p, __VA_ARGS__);        \
+        case 9: return FN<T, 18>(p, __VA_ARGS__);        \
+        case 10: return FN<T, 20>(p, __VA_ARGS__);       \
+        default: return NFFT3_ERR_INVALID_ARG;           \
+    }
+
 }  // namespace nfft3
