@@ -30,6 +30,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_PEAK_TFS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (published, packed)
+# LDS read rate: 256 B/clk/CU (ds_read_b128, measured) x 256 CUs x 2.4 GHz
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
 
 
 def log(msg):
@@ -83,6 +85,55 @@ def recorded_traffic(form):
     return None
 
 
+def form_roofline(r, N, M, copy_gbs):
+    """Roofline of the dominant kernel of one form's step (the window sums
+    at N = 256^3, M = 1e7), seen three ways:
+      hbm: algorithmic bytes (grid read once, n^3 elt; per point x 24 B,
+           permutation 4 B, result elt) per launch / launch time;
+      alu: algorithmic flops of the separable window sum, 4 [(2m)^3 + (2m)^2 +
+           2m] per point (real weight x complex value = 2 FMAs per term over x,
+           then y, then z), against the vector FMA peak without packed FP32
+           (78.6 TFLOP/s, FP32 and FP64 alike; the published 157.3 TFLOP/s
+           FP32 figure needs packed FP32 instructions, which this build
+           disables) -- the published FP32 figure is reported beside it;
+      lds: the (2m)^3 stencil values every point reads from LDS (elt each)
+           against 256 B/clk/CU (the measured ds_read_b128 rate) x 256 CUs x
+           2.4 GHz.
+    `primary` is the bound that applies: HBM for the FP32 form (the window
+    sums are balanced between HBM and VALU there), FP64 VALU for the FP64 form."""
+    m = r["m"]
+    elt = 8 if r["dtype"] == torch_complex64() else 16
+    n3 = float(np.prod(r["n"]))
+    W = 2 * m
+    ms = r["ms_interp"]
+    t = ms * 1e-3
+    alg_bytes = n3 * elt + M * (24 + 4 + elt)
+    gbs = alg_bytes / t / 1e9
+    form = "fp32" if elt == 8 else "fp64"
+    hbm = {"kernel": "interp (window sums)", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(form), "alg_bytes_per_launch": alg_bytes,
+           "ms_per_launch": ms, "achievable_copy_gbs": copy_gbs, "frac_of_achievable": gbs / copy_gbs}
+    fpp = 4.0 * (W ** 3 + W ** 2 + W)
+    tfs = M * fpp / t / 1e12
+    alu = {"kernel": "interp (window sums)", "bound": "alu", "achieved": tfs, "peak": VALU_PEAK_TFS,
+           "unit": "TFLOP/s", "frac": tfs / VALU_PEAK_TFS, "flops_per_point": fpp, "flops_per_launch": M * fpp,
+           "peak_note": "vector FMA rate without packed FP32 (256 CUs x 64 lanes x 2 flops x 2.4 GHz)"}
+    if elt == 8:
+        alu["published_fp32_peak"] = FP32_PEAK_TFLOPS
+        alu["frac_of_published_fp32_peak"] = tfs / FP32_PEAK_TFLOPS
+    lds_bytes = M * float(W ** 3) * elt
+    tbs = lds_bytes / t / 1e12
+    lds = {"kernel": "interp (window sums)", "bound": "lds", "achieved": tbs, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+           "frac": tbs / LDS_PEAK_TBS, "bytes_per_launch": lds_bytes}
+    primary = dict(hbm, alu=alu, lds=lds) if elt == 8 else dict(alu, hbm=hbm, lds=lds)
+    return {"hbm": hbm, "alu": alu, "lds": lds, "primary": primary}
+
+
+def torch_complex64():
+    import torch
+    return torch.complex64
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +165,26 @@ def cpu_model() -> str:
     except OSError:
         pass
     return f"{name} ({os.cpu_count()} logical CPUs)"
+
+
+def median(v):
+    v = sorted(v)
+    n = len(v)
+    return 0.5 * (v[(n - 1) // 2] + v[n // 2])
+
+
+def event_times(torch, stream, fn, reps):
+    """Run fn() reps times back to back on `stream`, with a HIP event before
+    the first and after every call; returns (per-call ms list, total ms)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    return per, ev[0].elapsed_time(ev[-1])
 
 
 def copy_bandwidth(torch, dev, stream, mib=1024, reps=5):
@@ -260,56 +331,30 @@ def main():
         for _ in range(args.warmup):
             plan.trafo(fhd, out=out)
         torch.cuda.synchronize()
-        # timed region: K whole steps
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
+        # timed region: K whole steps, one event between consecutive steps
         w0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            plan.trafo(fhd, out=out)
-        e1.record(stream)
-        torch.cuda.synchronize()
+        step_ms, total_ms = event_times(torch, stream, lambda: plan.trafo(fhd, out=out), args.steps)
         wall = time.perf_counter() - w0
-        ms_step = e0.elapsed_time(e1) / args.steps
+        ms_step = median(step_ms)
         # per-stage launch durations (HIP events on the plan's stream)
-        ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ga.record(stream)
-        for _ in range(args.steps):
-            plan.stage_grid(fhd)
-        gb.record(stream)
-        ia, ib = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ia.record(stream)
-        for _ in range(args.steps):
-            plan.stage_interp(out=out)
-        ib.record(stream)
-        torch.cuda.synchronize()
-        ms_grid = ga.elapsed_time(gb) / args.steps
-        ms_interp = ia.elapsed_time(ib) / args.steps
+        ms_grid = median(event_times(torch, stream, lambda: plan.stage_grid(fhd), args.steps)[0])
+        ms_interp = median(event_times(torch, stream, lambda: plan.stage_interp(out=out), args.steps)[0])
         extra = {}
         if not args.no_extras:
             # adjoint (type-1: spread + adjoint FFT passes + truncate) and the
             # point gradient on the same plan and points
             G = out.clone()
             adj = torch.empty_like(fhd)
-            reps = max(1, args.steps // 2)
+            reps = max(3, args.steps // 2)
             plan.adjoint(G, out=adj)
-            aa, ab = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            aa.record(stream)
-            for _ in range(reps):
-                plan.adjoint(G, out=adj)
-            ab.record(stream)
+            ms_adj = median(event_times(torch, stream, lambda: plan.adjoint(G, out=adj), reps)[0])
+            ms_spread = median(event_times(torch, stream, lambda: plan.stage_spread(G), reps)[0])
             plan.grad_points(fhd, G)
-            qa, qb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            qa.record(stream)
-            for _ in range(reps):
-                gx = plan.grad_points(fhd, G)
-            qb.record(stream)
-            torch.cuda.synchronize()
-            extra = {"adjoint_ms": aa.elapsed_time(ab) / reps, "grad_points_ms": qa.elapsed_time(qb) / reps}
-            del G, adj, gx
+            ms_gx = median(event_times(torch, stream, lambda: plan.grad_points(fhd, G), reps)[0])
+            extra = {"adjoint_ms": ms_adj, "spread_stage_ms": ms_spread, "grad_points_ms": ms_gx}
+            del G, adj
         f = out[torch.from_numpy(sample).to(dev)].cpu().numpy() if len(sample) else None
-        results[form] = dict(m=m, dtype=dt, ms_step=ms_step, wall_s=wall, t_set=t_set, t_set2=t_set2, ms_grid=ms_grid,
+        results[form] = dict(m=m, dtype=dt, ms_step=ms_step, ms_step_mean=total_ms / args.steps, wall_s=wall, t_set=t_set, t_set2=t_set2, ms_grid=ms_grid,
                              ms_interp=ms_interp, f_sample=f, n=plan.n, tuning=plan.tuning(), extra=extra)
         log(f"{form} m={m}: {ms_step:.3f} ms/step ({M / ms_step * 1e3:.3e} pts/s); grid stage {ms_grid:.3f} ms, "
             f"interp stage {ms_interp:.3f} ms; set_points {t_set * 1e3:.1f} ms")
@@ -349,26 +394,7 @@ def main():
 
     main_form = "fp32" if "fp32" in results else forms[0]
     r = results[main_form]
-    elt = 8 if main_form == "fp32" else 16
-    n3 = float(np.prod(r["n"]))
-    # algorithmic bytes per launch
-    interp_bytes = n3 * elt + M * (24 + 4 + elt)                 # grid once + x, perm, f
-    Nn = float(N)
-    nn = float(r["n"][0])
-    fft_bytes = elt * (Nn ** 3 + 2 * Nn * Nn * nn + 2 * Nn * nn * nn + nn ** 3)   # pruned passes
-    if r["ms_interp"] >= r["ms_grid"]:
-        dom, ms_dom, bytes_dom = "interp (window sums)", r["ms_interp"], interp_bytes
-    else:
-        dom, ms_dom, bytes_dom = "grid (deconvolve + pruned 3-D FFT)", r["ms_grid"], fft_bytes
-    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
-    # the window sums as an arithmetic kernel: every stencil term is a real
-    # weight times a complex value (2 FMAs = 4 flops), (2m)^3 terms per point
-    interp_flops = M * (2 * r["m"]) ** 3 * 4.0
-    alu = None
-    if dom.startswith("interp"):
-        tfs = interp_flops / (ms_dom * 1e-3) / 1e12
-        alu = {"bound": "alu", "achieved": tfs, "peak": VALU_PEAK_TFS, "unit": "TFLOP/s",
-               "frac": tfs / VALU_PEAK_TFS, "flops_per_launch": interp_flops}
+    rooflines = {form: form_roofline(rr, N, M, copy_gbs) for form, rr in results.items()}
     line = {
         "metric": "NFFT points/sec at N=256^3, M=1e7 (FP32 m=4 vs FP64 m=8) at stated rel-l2 error",
         "value": M / (r["ms_step"] * 1e-3),
@@ -386,11 +412,8 @@ def main():
                                f"(50% uniform, 50% in 16 Gaussian clusters std 0.02), sigma=2, "
                                f"{main_form} m={r['m']}; points set once, step = trafo",
                    "N": N, "M": M, "sigma": 2.0, "m": r["m"], "parallelism": "single GPU"},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(main_form) if dom.startswith("interp") else None,
-                     "alg_bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom,
-                     "achievable_copy_gbs": copy_gbs, "frac_of_achievable": achieved / copy_gbs, "alu": alu},
+        "roofline": dict(rooflines[main_form]["hbm"], alu=rooflines[main_form]["alu"],
+                         lds=rooflines[main_form]["lds"]),
         "cpu_baseline": cpu,
         "forms": {},
     }
@@ -403,6 +426,8 @@ def main():
             "wall_s_timed": rr["wall_s"],
             "tile": rr["tuning"][0], "points_per_item": rr["tuning"][1], **rr["extra"],
             "rel_l2": errs.get(form, (None, None))[0], "rel_linf": errs.get(form, (None, None))[1],
+            "ms_per_step_mean": rr["ms_step_mean"],
+            "roofline": rooflines[form]["primary"],
         }
     if extras:
         line["extras"] = extras

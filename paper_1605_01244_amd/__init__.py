@@ -61,6 +61,8 @@ class Plan:
         self.n = tuple(int(v) for v in n)
         self.M = 0
         self.epoch = 0
+        self._pts_key = None     # identity of the tensor the points came from
+        self._pts_ref = None     # held so its memory cannot be reused meanwhile
 
     # -- helpers -------------------------------------------------------
     def _bind_stream(self):
@@ -81,6 +83,13 @@ class Plan:
             raise ValueError(f"expected {count * self.M} values, got {f.numel()}")
         return f.contiguous()
 
+    @staticmethod
+    def _out(out: torch.Tensor) -> torch.Tensor:
+        # the library writes a dense block at the tensor's first address
+        if not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor")
+        return out
+
     def close(self):
         if self._h:
             lib.nfft3_destroy(self._h)
@@ -99,17 +108,35 @@ class Plan:
             raise ValueError("points must have shape (M, 3)")
         if x.dtype != torch.float64 or x.device != self.device:
             raise TypeError("points must be float64 on the plan's device")
+        key = self._key(x)
         x = x.contiguous()
         self._bind_stream()
+        self._pts_key = self._pts_ref = None
+        self.epoch += 1
         check(lib.nfft3_set_points(self._h, x.shape[0], _ptr(x)), "nfft3_set_points")
         self.M = int(x.shape[0])
-        self.epoch += 1
+        self._pts_key, self._pts_ref = key, x
+
+    @staticmethod
+    def _key(x: torch.Tensor):
+        """Storage, view geometry and version counter: equal keys of a held
+        tensor mean the same, unmodified coordinates."""
+        return (x.untyped_storage().data_ptr(), x.storage_offset(), tuple(x.shape), x.stride(), x._version)
+
+    def set_points_if_changed(self, x: torch.Tensor) -> bool:
+        """set_points(x) unless the plan's points were set from this very
+        tensor (same storage and view) and it was not modified since.
+        Returns True if the points were (re)sorted."""
+        if self._pts_key is not None and self._pts_key == self._key(x) and self.M == x.shape[0]:
+            return False
+        self.set_points(x)
+        return True
 
     def trafo(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         fhat = self._coeffs(fhat)
         if out is None:
             out = torch.empty(self.M, dtype=self.dtype, device=self.device)
-        self._values(out)
+        self._values(self._out(out))
         self._bind_stream()
         check(lib.nfft3_trafo(self._h, _ptr(fhat), _ptr(out)), "nfft3_trafo")
         return out
@@ -127,7 +154,7 @@ class Plan:
         f = self._values(f)
         if out is None:
             out = torch.empty(self.N, dtype=self.dtype, device=self.device)
-        self._coeffs(out)
+        self._coeffs(self._out(out))
         self._bind_stream()
         check(lib.nfft3_adjoint(self._h, _ptr(f), _ptr(out)), "nfft3_adjoint")
         return out
@@ -151,6 +178,7 @@ class Plan:
         if int(M.value) != self.M:      # the points were dropped
             self.M = int(M.value)
             self.epoch += 1
+            self._pts_key = self._pts_ref = None
 
     def tuning(self):
         t, i = ctypes.c_int(), ctypes.c_int()
@@ -167,10 +195,11 @@ class Plan:
         out = torch.empty(x.shape[0], dtype=self.dtype, device=self.device)
         t, i = ctypes.c_int(), ctypes.c_int()
         self._bind_stream()
+        self._pts_key = self._pts_ref = None
+        self.epoch += 1
         check(lib.nfft3_autotune(self._h, x.shape[0], _ptr(x), _ptr(fhat), _ptr(out), int(reps),
                                  ctypes.byref(t), ctypes.byref(i)), "nfft3_autotune")
         self.M = int(x.shape[0])
-        self.epoch += 1
         return int(t.value), int(i.value)
 
     # -- stage access (tests, benchmarks) ------------------------------------
@@ -182,7 +211,7 @@ class Plan:
     def stage_interp(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.M, dtype=self.dtype, device=self.device)
-        self._values(out)
+        self._values(self._out(out))
         self._bind_stream()
         check(lib.nfft3_stage_interp(self._h, _ptr(out)), "nfft3_stage_interp")
         return out
@@ -233,7 +262,8 @@ class _Type2(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, fhat, x, plan):
-        plan.set_points(x.detach())
+        # the sort is the precomputation: redo it only for new or modified points
+        plan.set_points_if_changed(x.detach())
         ctx.plan = plan
         ctx.epoch = plan.epoch
         ctx.save_for_backward(fhat, x)

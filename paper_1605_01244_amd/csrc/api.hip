@@ -263,8 +263,10 @@ static int alloc_bins(nfft3_plan_impl *p, int T) {
     p->bins.ntx = (int)((p->n[2] + p->bins.Bx - 1) / p->bins.Bx);
     const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
     const int64_t nb = ntiles * p->n[0];
-    p->bins.nbins = nb;
     const int64_t nc = nb * kBinCopies;
+    // counter indices (bin kBinCopies + copy) and sorted positions are int
+    if (nc + 1 > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
+    p->bins.nbins = nb;
     NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nc));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nc + 1)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nc / 1024 + 2)));

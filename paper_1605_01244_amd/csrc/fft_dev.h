@@ -1,6 +1,7 @@
 // Device code of the FFT passes (deconvolve + zero-pad + Stockham passes and
-// the transposed adjoint passes), shared by the stand-alone pass kernels and
-// the persistent batched kernel.  See fft.hip for the pass structure.
+// the transposed adjoint passes), shared by the single-plan pass kernels
+// (fft.hip) and the batched per-length launches (batch.hip).  See fft.hip for
+// the pass structure.
 #pragma once
 #include "internal.h"
 

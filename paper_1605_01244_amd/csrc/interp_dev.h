@@ -1,6 +1,6 @@
 // Device code of the window sums (plane streaming over (tile, z)-sorted
-// points), shared by the stand-alone kernels and the persistent batched
-// kernel.  See interp.hip for the scheme.
+// points), shared by the single-plan kernels (interp.hip) and the batched
+// window-sum launch (batch.hip).  See interp.hip for the scheme.
 #pragma once
 #include <numeric>
 
@@ -152,8 +152,8 @@ __device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int
     it.active = it.p < hi;
     // points are sorted by z-cell: the first and last give the range
     float dummy;
-    const int zmin = cell_frac<float>(a.xs[3 * lo], a.n0, dummy);
-    const int zmax = cell_frac<float>(a.xs[3 * (hi - 1)], a.n0, dummy);
+    const int zmin = cell_frac<float>(a.xs[3 * (int64_t)lo], a.n0, dummy);
+    const int zmax = cell_frac<float>(a.xs[3 * ((int64_t)hi - 1)], a.n0, dummy);
     it.zbeg = zmin - m + 1;
     it.nplanes = zmax - zmin + 2 * m;
     it.PY = a.By + 2 * m - 1;
@@ -383,7 +383,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
 #pragma unroll
         for (int r = 0; r < WG; ++r) { d1[k][r] = 0; e2[r] = 0; }
         if (active) {
-            const double *xp = a.xs + 3 * pk;
+            const double *xp = a.xs + 3 * (int64_t)pk;
             T f1, f2;
             const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
             const int yc = cell_frac<T>(xp[1], a.n1, f1);

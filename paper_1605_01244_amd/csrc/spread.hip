@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
 #pragma unroll
         for (int r = 0; r < W; ++r) { w1[k][r] = 0; w2[k][r] = 0; }
         if (pk < hi) {
-            const double *xp = a.xs + 3 * pk;
+            const double *xp = a.xs + 3 * (int64_t)pk;
             T f1, f2;
             const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
             const int yc = cell_frac<T>(xp[1], a.n1, f1);

@@ -72,6 +72,29 @@ def test_windowed_map_within_error_estimate(m):
     assert err <= max(bound, 1e-13 * np.sum(np.abs(fh))), (m, err, bound)
 
 
+@pytest.mark.parametrize("sigma,ms", [(2.0, (2, 3, 4, 5, 6, 7)), (1.5, (2, 3, 4, 5, 6, 7, 8))])
+def test_error_estimate_is_tight_on_band_edge_modes(sigma, ms):
+    """Both sides of E(m, sigma): single modes at the corners and edges of
+    I_N (where the window's transform is smallest, so the aliasing error is
+    largest) and an interior mode, at random points.  The worst error of the
+    windowed map, relative to ||fhat||_1 = 1, lies within a factor 4 of E on
+    either side (measured 0.49 - 1.26 E); a wrong factor or exponent in E
+    (e.g. (1 - 1/sigma) in place of its square root, 180x looser at m = 4)
+    fails one side.  m = 8 at sigma = 2 is left out: there E = 4e-14 is
+    below the FP64 rounding of the numpy steps."""
+    N = (16, 16, 16)
+    x = _pts(400, 5)
+    for m in ms:
+        worst = 0.0
+        for kstar in [(0, 0, 0), (0, 8, 0), (15, 15, 15), (0, 0, 8), (8, 8, 8)]:
+            fh = np.zeros(N, dtype=np.complex128)
+            fh[kstar] = 1.0
+            err = np.max(np.abs(ns.trafo(fh, x, m, sigma) - oracle.ndft_trafo(fh, x)))
+            worst = max(worst, err)
+        E = ns.pst_error_bound(m, sigma)
+        assert E / 4 <= worst <= 4 * E, (sigma, m, worst, E, worst / E)
+
+
 def test_error_decreases_with_m():
     N = (16, 16, 16)
     fh = _coeffs(N, 80)
@@ -121,3 +144,29 @@ def test_grad_steps_vs_direct_derivative():
     got = ns.grad_points(fh, x, 8, 2.0)
     l2, _ = oracle.rel_errors(got, ref)
     assert l2 < 1e-11, l2
+
+
+_BOUND_MUTANTS = {
+    # (1 - 1/sigma) in place of its square root in the exponent
+    "exponent_without_sqrt": lambda m, s: 4 * math.pi * (math.sqrt(m) + m) * (1 - 1 / s) ** 0.25
+    * math.exp(-2 * math.pi * m * (1 - 1 / s)),
+    "dropped_4pi": lambda m, s: _TRUE_BOUND(m, s) / (4 * math.pi),
+    "dropped_m_factor": lambda m, s: _TRUE_BOUND(m, s) / (math.sqrt(m) + m),
+    "pi_for_2pi": lambda m, s: 4 * math.pi * (math.sqrt(m) + m) * (1 - 1 / s) ** 0.25
+    * math.exp(-math.pi * m * math.sqrt(1 - 1 / s)),
+    "m_off_by_one": lambda m, s: _TRUE_BOUND(m + 1, s),
+}
+_TRUE_BOUND = ns.pst_error_bound
+
+
+@pytest.mark.parametrize("mutant", sorted(_BOUND_MUTANTS))
+def test_planted_mistakes_in_error_estimate(mutant, monkeypatch):
+    """Each plausible mistake in E(m, sigma) fails the two-sided pin."""
+    monkeypatch.setattr(ns, "pst_error_bound", _BOUND_MUTANTS[mutant])
+    failed = False
+    for sigma, ms in [(2.0, (2, 4, 6)), (1.5, (3, 5, 8))]:
+        try:
+            test_error_estimate_is_tight_on_band_edge_modes(sigma, ms)
+        except AssertionError:
+            failed = True
+    assert failed, mutant
