@@ -95,6 +95,17 @@ int nfft3_set_stream(nfft3_plan_t p, void *stream);
  * coordinate is NaN or infinite. */
 int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x_dev);
 
+/* Are the plan's sorted points still those of x_dev ((M, 3) FP64 device
+ * array)?  *unchanged (host int) = 1 when the plan holds M points and, for
+ * every point, the folded coordinates kept by the last nfft3_set_points equal
+ * the fold of x_dev's current coordinates bit for bit (so a new
+ * nfft3_set_points would produce the same sorted state); 0 otherwise (also
+ * when the plan has no points or another M).  A caller that re-evaluates at
+ * possibly unchanged points (an autograd forward) uses it to skip the sort,
+ * the precomputation of Sec. 2.2.1's method.  One pass over the points;
+ * synchronises the plan's stream. */
+int nfft3_points_unchanged(nfft3_plan_t p, int64_t M, const double *x_dev, int *unchanged);
+
 /* Type-2 transform (the evaluation of Sec. 2.2.1):
  * f_dev[j] ~ sum_k fhat_k exp(-2 pi i k.x_j), j in the caller's point order.
  * fhat_dev: N0*N1*N2 complex, f_dev: M complex (dtype of the plan).

@@ -61,8 +61,6 @@ class Plan:
         self.n = tuple(int(v) for v in n)
         self.M = 0
         self.epoch = 0
-        self._pts_key = None     # identity of the tensor the points came from
-        self._pts_ref = None     # held so its memory cannot be reused meanwhile
 
     # -- helpers -------------------------------------------------------
     def _bind_stream(self):
@@ -108,27 +106,30 @@ class Plan:
             raise ValueError("points must have shape (M, 3)")
         if x.dtype != torch.float64 or x.device != self.device:
             raise TypeError("points must be float64 on the plan's device")
-        key = self._key(x)
         x = x.contiguous()
         self._bind_stream()
-        self._pts_key = self._pts_ref = None
         self.epoch += 1
+        self.M = 0
         check(lib.nfft3_set_points(self._h, x.shape[0], _ptr(x)), "nfft3_set_points")
         self.M = int(x.shape[0])
-        self._pts_key, self._pts_ref = key, x
-
-    @staticmethod
-    def _key(x: torch.Tensor):
-        """Storage, view geometry and version counter: equal keys of a held
-        tensor mean the same, unmodified coordinates."""
-        return (x.untyped_storage().data_ptr(), x.storage_offset(), tuple(x.shape), x.stride(), x._version)
 
     def set_points_if_changed(self, x: torch.Tensor) -> bool:
-        """set_points(x) unless the plan's points were set from this very
-        tensor (same storage and view) and it was not modified since.
-        Returns True if the points were (re)sorted."""
-        if self._pts_key is not None and self._pts_key == self._key(x) and self.M == x.shape[0]:
-            return False
+        """set_points(x) unless the plan's sorted points are exactly those of
+        x (nfft3_points_unchanged compares every folded coordinate on the
+        device, so writes that bypass the tensor's version counter, such as
+        through .data, are seen).  Returns True if the points were sorted."""
+        if x.dim() != 2 or x.shape[1] != 3:
+            raise ValueError("points must have shape (M, 3)")
+        if x.dtype != torch.float64 or x.device != self.device:
+            raise TypeError("points must be float64 on the plan's device")
+        if self.M == x.shape[0]:
+            xc = x.contiguous()
+            same = ctypes.c_int(0)
+            self._bind_stream()
+            check(lib.nfft3_points_unchanged(self._h, xc.shape[0], _ptr(xc), ctypes.byref(same)),
+                  "nfft3_points_unchanged")
+            if same.value:
+                return False
         self.set_points(x)
         return True
 
@@ -178,7 +179,6 @@ class Plan:
         if int(M.value) != self.M:      # the points were dropped
             self.M = int(M.value)
             self.epoch += 1
-            self._pts_key = self._pts_ref = None
 
     def tuning(self):
         t, i = ctypes.c_int(), ctypes.c_int()
@@ -195,8 +195,8 @@ class Plan:
         out = torch.empty(x.shape[0], dtype=self.dtype, device=self.device)
         t, i = ctypes.c_int(), ctypes.c_int()
         self._bind_stream()
-        self._pts_key = self._pts_ref = None
         self.epoch += 1
+        self.M = 0
         check(lib.nfft3_autotune(self._h, x.shape[0], _ptr(x), _ptr(fhat), _ptr(out), int(reps),
                                  ctypes.byref(t), ctypes.byref(i)), "nfft3_autotune")
         self.M = int(x.shape[0])

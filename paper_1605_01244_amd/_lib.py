@@ -51,6 +51,7 @@ def _load() -> ctypes.CDLL:
         "nfft3_set_stream": ([vp, vp], ci),
         "nfft3_set_points": ([vp, i64, vp], ci),
         "nfft3_trafo": ([vp, vp, vp], ci),
+        "nfft3_points_unchanged": ([vp, i64, vp, ctypes.POINTER(ci)], ci),
         "nfft3_adjoint": ([vp, vp, vp], ci),
         "nfft3_grad_points": ([vp, vp, vp, vp], ci),
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),

@@ -388,6 +388,15 @@ int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x) {
     return NFFT3_OK;
 }
 
+int nfft3_points_unchanged(nfft3_plan_t p, int64_t M, const double *x, int *unchanged) {
+    if (!p || !unchanged) return NFFT3_ERR_NULL;
+    *unchanged = 0;
+    if (M < 0) return NFFT3_ERR_INVALID_ARG;
+    if (!p->have_points || M != p->M) return NFFT3_OK;
+    if (M > 0 && !x) return NFFT3_ERR_NULL;
+    return launch_points_equal(p, M, x, unchanged);
+}
+
 int nfft3_trafo(nfft3_plan_t p, const void *fhat, void *f) {
     if (!p) return NFFT3_ERR_NULL;
     if (!p->have_points) return NFFT3_ERR_NO_POINTS;
@@ -447,6 +456,7 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat,
         if (plans[t]->dtype != plans[0]->dtype) return NFFT3_ERR_DTYPE;
         if (plans[t]->m != plans[0]->m || plans[t]->sigma != plans[0]->sigma || plans[t]->m > 8)
             return NFFT3_ERR_INVALID_ARG;
+        if (plans[t]->device != plans[0]->device) return NFFT3_ERR_INVALID_ARG;
         for (int u = 0; u < t; ++u)
             if (plans[u] == plans[t]) return NFFT3_ERR_INVALID_ARG;
     }

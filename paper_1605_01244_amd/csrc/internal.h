@@ -210,6 +210,8 @@ int launch_grid_forward(nfft3_plan_impl *p, const void *fhat, void *grid, int de
 int launch_grid_adjoint(nfft3_plan_impl *p, void *grid, void *fhat);
 // points (points.hip)
 int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x);
+// *equal = 1 when the sorted points are those of x (no new sort needed)
+int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equal);
 // window sums and their point derivative (interp.hip)
 int launch_interp(nfft3_plan_impl *p, const void *grid, void *f);
 int launch_grad(nfft3_plan_impl *p, const void *grid, const void *G, double *grad_x);

@@ -149,6 +149,44 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
     perm[pos] = (int)j;
 }
 
+// ---- do the sorted points still describe x? ------------------------------
+// Sorted position q holds fold(x[perm[q]]) from the last sort.  If every
+// position still equals the fold of the caller's current coordinates (bit for
+// bit), a new sort would yield the same bins and items, so it can be skipped.
+// Any difference (or a NaN, which never compares equal) sets bit 1 of flag.
+__global__ void __launch_bounds__(kPtThreads)
+points_equal_kernel(const double *__restrict__ x, int64_t M, const double *__restrict__ xs,
+                    const int *__restrict__ perm, int *__restrict__ flag) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
+    const int64_t j = perm[q];
+    bool same = j >= 0 && j < M;
+    if (same) {
+        const double *xp = x + 3 * j;
+        const double *sp = xs + 3 * q;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            same = same && __double_as_longlong(fold_unit(xp[d])) == __double_as_longlong(sp[d]);
+    }
+    if (!same) atomicOr(flag + 1, 2);
+}
+
+int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equal) {
+    hipStream_t s = p->stream;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, s, p->flag, (int64_t)16, 0);
+    NFFT3_LAUNCH_CHECK("fill_int_kernel");
+    if (M > 0) {
+        hipLaunchKernelGGL(points_equal_kernel, dim3((unsigned)((M + kPtThreads - 1) / kPtThreads)),
+                           dim3(kPtThreads), 0, s, x, M, p->xs, p->perm, p->flag);
+        NFFT3_LAUNCH_CHECK("points_equal_kernel");
+    }
+    int w = 0;
+    NFFT3_HIP_TRY(hipMemcpyAsync(&w, p->flag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    NFFT3_HIP_TRY(hipStreamSynchronize(s));
+    *equal = (w & 2) ? 0 : 1;
+    return NFFT3_OK;
+}
+
 // ---- work items: walk each tile column's z-cells (one wave per tile) ------
 // A new item starts when adding the next cell would exceed maxpts points or
 // the item would span more than kItemZ z-cells; a cell holding more than

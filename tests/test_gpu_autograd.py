@@ -105,3 +105,33 @@ def test_backward_after_points_replaced(nf):
     ref = oracle.ndft_adjoint(G.cpu().numpy(), x1.cpu().numpy(), N)
     l2, _ = rel(fh.grad.cpu().numpy(), ref)
     assert l2 <= tol(6, 2.0, "c128")
+
+
+def test_forward_resorts_only_changed_points(nf):
+    """The autograd forward skips the sort only when every folded coordinate
+    still equals the plan's sorted copy: an unchanged tensor, or one shifted
+    by whole periods (same folded values), is not re-sorted; a write through
+    .data (which bypasses the version counter) and a different M are."""
+    import torch
+    N = (10, 8, 12)
+    plan = nf.Plan(N, m=6, dtype=torch.complex128, device="cuda:0")
+    fh_np = rand_coeffs(N, 20)
+    fh = to_dev(fh_np, "c128")
+    # multiples of 2^-20, so x + 2 is exact and folds back to x bit for bit
+    x_np = np.round(rand_points(300, 21) * 2.0**20) / 2.0**20
+    x = to_dev(x_np)
+    log("points cache")
+    assert plan.set_points_if_changed(x) is True
+    assert plan.set_points_if_changed(x) is False
+    assert plan.set_points_if_changed(x.clone()) is False
+    assert plan.set_points_if_changed(x + 2.0) is False      # folds to the same coordinates
+    x.data[17, 1] += 1e-3                                      # not seen by the version counter
+    f = nf.type2(fh, x, plan).cpu().numpy()
+    ref = oracle.ndft_trafo(fh_np, x.cpu().numpy())
+    l2, li = rel(f, ref)
+    assert l2 <= tol(6, 2.0, "c128") and li <= tol(6, 2.0, "c128"), (l2, li)
+    assert plan.set_points_if_changed(x[:200]) is True
+    assert plan.M == 200
+    ab = torch.tensor([[0.1, float("nan"), 0.2]], dtype=torch.float64, device="cuda:0")
+    with pytest.raises(nf.NFFT3Error):
+        plan.set_points_if_changed(ab)
