@@ -64,7 +64,8 @@ enum nfft3_status {
     NFFT3_ERR_NO_POINTS = -4,   /* trafo/adjoint/grad before nfft3_set_points    */
     NFFT3_ERR_NONFINITE = -5,   /* a point coordinate is NaN or infinite         */
     NFFT3_ERR_HIP = -6,         /* HIP runtime error (see nfft3_last_hip_error)  */
-    NFFT3_ERR_NULL = -7         /* NULL plan or NULL required pointer            */
+    NFFT3_ERR_NULL = -7,        /* NULL plan or NULL required pointer            */
+    NFFT3_ERR_CAPACITY = -8     /* batch too large for nfft3_batch_trafo_noalloc */
 };
 
 /* Create a plan for coefficient sizes N[0..2] (host array).
@@ -150,6 +151,26 @@ int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int 
  * (the launch descriptors are staged from host memory). */
 int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
                       void *const *out_dev, int deriv_mask);
+
+/* nfft3_batch_trafo without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results
+ * (bit for bit) as nfft3_batch_trafo; it calls no hipMalloc, hipFree or
+ * allocating library routine.  The launch descriptors go to a static device
+ * array of NFFT3_BATCH_SCRATCH_BYTES per GPU (held until the process ends)
+ * instead of a library-allocated buffer: about 560 bytes per (plan, field)
+ * transform, so roughly 450 transforms per call; a larger batch returns
+ * NFFT3_ERR_CAPACITY before any work is enqueued.  Every plan must already
+ * hold the grids its fields need: one per plan for deriv_mask = 0, one per
+ * evaluated field otherwise (made by an earlier nfft3_batch_trafo call with
+ * at least these fields); else NFFT3_ERR_INVALID_ARG.  All calls on one GPU
+ * share the array, which keeps the last call's descriptors; calls (of either
+ * batch entry point) on one GPU are serialised by a lock in the library,
+ * each holding it until its work has finished (the call synchronises before
+ * it returns), so host threads overlapping their calls do not race on it. */
+#define NFFT3_BATCH_SCRATCH_BYTES (256 * 1024)
+int nfft3_batch_trafo_noalloc(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
+                              void *const *out_dev, int deriv_mask);
 
 /* ---- Tuning of the point binning (not in the paper; the window sums of
  * Sec. 2.2.1 at the plan's points are computed the same way for every

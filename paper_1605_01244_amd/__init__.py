@@ -235,24 +235,40 @@ class Plan:
         check(lib.nfft3_grid_copy(self._h, _ptr(g), 1), "nfft3_grid_copy")
 
 
-def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0):
+def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0,
+                out: Sequence[torch.Tensor] | None = None, allocate: bool = True):
     """Evaluate every plan's coefficients (and derivative fields) together:
     per stage one launch per transform length over all (plan, field) pairs
     of that length (the window sums: one launch).  Returns a list of
-    (1 + popcount(mask), M_t) tensors."""
+    (1 + popcount(mask), M_t) tensors (`out`, when given: contiguous tensors
+    of those shapes).  allocate=False calls nfft3_batch_trafo_noalloc, which
+    allocates no device memory (the plans must already hold their field
+    grids)."""
     T = len(plans)
     if T != len(fhats):
         raise ValueError("one coefficient array per plan")
     k = 1 + bin(deriv_mask & 7).count("1")
     fh = [p._coeffs(f) for p, f in zip(plans, fhats)]
-    outs = [torch.empty((k, p.M), dtype=p.dtype, device=p.device) for p in plans]
+    if out is None:
+        outs = [torch.empty((k, p.M), dtype=p.dtype, device=p.device) for p in plans]
+    else:
+        outs = list(out)
+        if len(outs) != T:
+            raise ValueError("one output tensor per plan")
+        for p, o in zip(plans, outs):
+            if tuple(o.shape) != (k, p.M) or o.dtype != p.dtype or o.device != p.device:
+                raise ValueError(f"output must be ({k}, {p.M}) {p.dtype} on {p.device}")
+            Plan._out(o)
     if T == 0:
         return outs
     plans[0]._bind_stream()
     H = (ctypes.c_void_p * T)(*[p._h.value for p in plans])
     F = (ctypes.c_void_p * T)(*[f.data_ptr() for f in fh])
     O = (ctypes.c_void_p * T)(*[o.data_ptr() for o in outs])
-    check(lib.nfft3_batch_trafo(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo")
+    if allocate:
+        check(lib.nfft3_batch_trafo(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo")
+    else:
+        check(lib.nfft3_batch_trafo_noalloc(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo_noalloc")
     return outs
 
 

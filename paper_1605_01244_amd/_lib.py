@@ -24,6 +24,7 @@ STATUS = {
     -5: "NFFT3_ERR_NONFINITE",
     -6: "NFFT3_ERR_HIP",
     -7: "NFFT3_ERR_NULL",
+    -8: "NFFT3_ERR_CAPACITY",
 }
 
 
@@ -50,12 +51,13 @@ def _load() -> ctypes.CDLL:
         "nfft3_plan": ([ctypes.POINTER(vp), i64p, ctypes.c_double, ci, ci, vp], ci),
         "nfft3_set_stream": ([vp, vp], ci),
         "nfft3_set_points": ([vp, i64, vp], ci),
-        "nfft3_trafo": ([vp, vp, vp], ci),
         "nfft3_points_unchanged": ([vp, i64, vp, ctypes.POINTER(ci)], ci),
+        "nfft3_trafo": ([vp, vp, vp], ci),
         "nfft3_adjoint": ([vp, vp, vp], ci),
         "nfft3_grad_points": ([vp, vp, vp, vp], ci),
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),
         "nfft3_batch_trafo": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
+        "nfft3_batch_trafo_noalloc": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
         "nfft3_set_tuning": ([vp, ci, ci], ci),
         "nfft3_get_tuning": ([vp, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
         "nfft3_autotune": ([vp, i64, vp, vp, vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),

@@ -444,8 +444,8 @@ int nfft3_grad_points(nfft3_plan_t p, const void *fhat, const void *G, double *g
     return launch_grad(p, p->grid, G, grad_x);
 }
 
-int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out,
-                      int mask) {
+static int batch_common(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out, int mask,
+                        bool noalloc) {
     if (T < 0 || mask < 0 || mask > 7) return NFFT3_ERR_INVALID_ARG;
     if (T == 0) return NFFT3_OK;
     if (!plans || !fhat || !out) return NFFT3_ERR_NULL;
@@ -461,7 +461,16 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat,
             if (plans[u] == plans[t]) return NFFT3_ERR_INVALID_ARG;
     }
     std::vector<nfft3_plan_impl *> pl(plans, plans + T);
-    return launch_batch(T, pl.data(), fhat, out, mask);
+    return launch_batch(T, pl.data(), fhat, out, mask, noalloc);
+}
+
+int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out, int mask) {
+    return batch_common(T, plans, fhat, out, mask, false);
+}
+
+int nfft3_batch_trafo_noalloc(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out,
+                              int mask) {
+    return batch_common(T, plans, fhat, out, mask, true);
 }
 
 const char *nfft3_strerror(int code) {
@@ -474,6 +483,7 @@ const char *nfft3_strerror(int code) {
         case NFFT3_ERR_NONFINITE: return "non-finite point coordinate";
         case NFFT3_ERR_HIP: return "HIP runtime error";
         case NFFT3_ERR_NULL: return "NULL plan or pointer";
+        case NFFT3_ERR_CAPACITY: return "launch descriptors exceed the static scratch of the no-allocation call";
         default: return "unknown status";
     }
 }

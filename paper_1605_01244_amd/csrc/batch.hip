@@ -16,6 +16,7 @@
 // bit.  (A single kernel over all lengths holds every specialisation's code
 // and ran several times slower.)
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "fft_dev.h"
@@ -120,12 +121,59 @@ static void launch_group_fft(const BatchGroup &g, const BatchXform *dxf, const i
     }
 }
 
-// device-side descriptors of the batched launcher (grown as needed, kept)
-static void *g_batch_buf = nullptr;
-static size_t g_batch_cap = 0;
+// Launch descriptors.  The allocating call keeps one device buffer per GPU,
+// grown as needed; the no-allocation call uses the file-scope array
+// `scratch` below.  Each call holds its GPU's lock until its work has
+// finished (the call synchronises before it returns), so calls on one GPU
+// from several host threads run one after another and never share a buffer
+// while it is in use.
+constexpr int kMaxDevices = 64;
+struct DescBuf {
+    void *buf = nullptr;
+    size_t cap = 0;
+};
+static std::mutex g_batch_mu[kMaxDevices];
+static DescBuf g_desc[kMaxDevices];
+
+// Descriptors of nfft3_batch_trafo_noalloc: a static device array, one copy
+// per GPU, kept until the process ends.  Host code never passes `scratch`
+// itself to a kernel or copy (on the host it only names the symbol): its
+// device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+constexpr size_t kBatchScratchBytes = NFFT3_BATCH_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+static void *g_scratch_ptr[kMaxDevices];
+
+// the device address of `scratch` on GPU dev (caller holds g_batch_mu[dev] and
+// has made dev the current device)
+static int scratch_address(int dev, void **ptr) {
+    if (!g_scratch_ptr[dev]) {
+        void *a = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            set_hip_error(e, "hipGetSymbolAddress(scratch)");
+            return NFFT3_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = a;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return NFFT3_OK;
+}
 
 template <typename T, int W, int PPT>
-static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask) {
+static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask,
+                        bool noalloc) {
+    const int dev = plans[0]->device;
+    if (dev < 0 || dev >= kMaxDevices) return NFFT3_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_batch_mu[dev]);
+    // allocations (allocating call) land on the plans' device
+    int cur_dev = 0;
+    NFFT3_HIP_TRY(hipGetDevice(&cur_dev));
+    struct Restore {
+        int dev;
+        ~Restore() { (void)hipSetDevice(dev); }
+    } restore{cur_dev};
+    if (cur_dev != dev) NFFT3_HIP_TRY(hipSetDevice(dev));
     std::vector<int> fields = {-1};
     for (int d = 0; d < 3; ++d)
         if (mask & (1 << d)) fields.push_back(d);
@@ -134,16 +182,22 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
     std::vector<BatchXform> xf((size_t)X);
     size_t lds_ip = 0;
     hipStream_t stream = plans[0]->stream;
+    bool missing_grids = false;
     for (int t = 0; t < T_; ++t) {
         nfft3_plan_impl *p = plans[t];
-        while ((int)p->extra_grids.size() < F - 1) {
-            void *g = nullptr;
-            NFFT3_HIP_TRY(hipMalloc(&g, (size_t)p->n[0] * p->n[1] * p->n[2] * p->elt));
-            p->extra_grids.push_back(g);
+        if (noalloc) {
+            missing_grids = missing_grids || (int)p->extra_grids.size() < F - 1;
+        } else {
+            while ((int)p->extra_grids.size() < F - 1) {
+                void *g = nullptr;
+                NFFT3_HIP_TRY(hipMalloc(&g, (size_t)p->n[0] * p->n[1] * p->n[2] * p->elt));
+                p->extra_grids.push_back(g);
+            }
         }
         for (int f = 0; f < F; ++f) {
             BatchXform &b = xf[(size_t)t * F + f];
-            void *grid = f == 0 ? p->grid : p->extra_grids[f - 1];
+            // (a missing grid is reported below, before anything is launched)
+            void *grid = (f == 0 || f - 1 >= (int)p->extra_grids.size()) ? p->grid : p->extra_grids[f - 1];
             b.rows = make_row_args<T>(p, fhat[t], grid, fields[f], kBRowThreads);
             b.c1 = make_col_args<T>(p, grid, 1, (int)p->N[1], (int)p->n[1], p->n[1] * p->n[2]);
             b.c0 = make_col_args<T>(p, grid, 0, (int)p->N[0], (int)p->n[0], p->n[2]);
@@ -211,17 +265,26 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
         if (g.stage == 3) g.lds = lds_ip;
     }
     const size_t need = off + sizeof(int) * ints.size();
-    if (need > g_batch_cap) {
-        if (g_batch_buf) {
-            NFFT3_HIP_TRY(hipStreamSynchronize(stream));
-            (void)hipFree(g_batch_buf);
+    char *base = nullptr;
+    if (noalloc) {
+        if (need > kBatchScratchBytes) return NFFT3_ERR_CAPACITY;
+        if (missing_grids) return NFFT3_ERR_INVALID_ARG;
+        void *sp = nullptr;
+        const int rc = scratch_address(dev, &sp);
+        if (rc) return rc;
+        base = (char *)sp;
+    } else {
+        DescBuf &d = g_desc[dev];
+        if (need > d.cap) {
+            // the previous call on this GPU synchronised before it released the lock
+            (void)hipFree(d.buf);
+            d.buf = nullptr;
+            d.cap = 0;
+            NFFT3_HIP_TRY(hipMalloc(&d.buf, need));
+            d.cap = need;
         }
-        g_batch_buf = nullptr;
-        g_batch_cap = 0;
-        NFFT3_HIP_TRY(hipMalloc(&g_batch_buf, need));
-        g_batch_cap = need;
+        base = (char *)d.buf;
     }
-    char *base = (char *)g_batch_buf;
     NFFT3_HIP_TRY(hipMemcpyAsync(base, xf.data(), sizeof(BatchXform) * X, hipMemcpyHostToDevice, stream));
     NFFT3_HIP_TRY(hipMemcpyAsync(base + off, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, stream));
     const BatchXform *dxf = (const BatchXform *)base;
@@ -248,15 +311,16 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
 }
 
 template <typename T, int W>
-static int batch_w(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask) {
+static int batch_w(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask,
+                   bool noalloc) {
     for (int t = 0; t < T_; ++t)
         if (plans[t]->sub.maxpts != plans[0]->sub.maxpts) return NFFT3_ERR_INVALID_ARG;
     if constexpr (W > 16) {
         return NFFT3_ERR_INVALID_ARG;
     } else {
         switch (plans[0]->sub.maxpts / kPsThreads) {
-            case 1: return batch_launch<T, W, 1>(T_, plans, fhat, out, mask);
-            case 2: return batch_launch<T, W, 2>(T_, plans, fhat, out, mask);
+            case 1: return batch_launch<T, W, 1>(T_, plans, fhat, out, mask, noalloc);
+            case 2: return batch_launch<T, W, 2>(T_, plans, fhat, out, mask, noalloc);
             default: return NFFT3_ERR_INVALID_ARG;
         }
     }
@@ -264,18 +328,19 @@ static int batch_w(int T_, nfft3_plan_impl *const *plans, const void *const *fha
 
 #define NFFT3_BATCH_M(T)                                          \
     switch (plans[0]->m) {                                        \
-        case 1: return batch_w<T, 2>(T_, plans, fhat, out, mask);  \
-        case 2: return batch_w<T, 4>(T_, plans, fhat, out, mask);  \
-        case 3: return batch_w<T, 6>(T_, plans, fhat, out, mask);  \
-        case 4: return batch_w<T, 8>(T_, plans, fhat, out, mask);  \
-        case 5: return batch_w<T, 10>(T_, plans, fhat, out, mask); \
-        case 6: return batch_w<T, 12>(T_, plans, fhat, out, mask); \
-        case 7: return batch_w<T, 14>(T_, plans, fhat, out, mask); \
-        case 8: return batch_w<T, 16>(T_, plans, fhat, out, mask); \
+        case 1: return batch_w<T, 2>(T_, plans, fhat, out, mask, noalloc);  \
+        case 2: return batch_w<T, 4>(T_, plans, fhat, out, mask, noalloc);  \
+        case 3: return batch_w<T, 6>(T_, plans, fhat, out, mask, noalloc);  \
+        case 4: return batch_w<T, 8>(T_, plans, fhat, out, mask, noalloc);  \
+        case 5: return batch_w<T, 10>(T_, plans, fhat, out, mask, noalloc); \
+        case 6: return batch_w<T, 12>(T_, plans, fhat, out, mask, noalloc); \
+        case 7: return batch_w<T, 14>(T_, plans, fhat, out, mask, noalloc); \
+        case 8: return batch_w<T, 16>(T_, plans, fhat, out, mask, noalloc); \
         default: return NFFT3_ERR_INVALID_ARG;                    \
     }
 
-int launch_batch(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask) {
+int launch_batch(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask,
+                 bool noalloc) {
     if (plans[0]->dtype == NFFT3_C128) { NFFT3_BATCH_M(double) }
     NFFT3_BATCH_M(float)
 }

@@ -220,7 +220,7 @@ int launch_spread(nfft3_plan_impl *p, const void *f, void *grid);
 int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);
 // batch (batch.hip)
 int launch_batch(int T, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out,
-                 int deriv_mask);
+                 int deriv_mask, bool noalloc);
 
 }  // namespace nfft3
 
