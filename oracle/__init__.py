@@ -11,6 +11,8 @@ Two parts:
   Sec. 2.2.1, evaluated in the one-loop order of eq. (Fs)), in C
   (``oracle/ndft.c``) with POSIX threads, reached through ctypes.  These are
   the reference every GPU result is compared with.
+* ``rgrid_eval`` -- the series at a rectilinear grid as the nested per-axis
+  sums of Sec. 2.1 (numpy FP64 matrix products with the E^d matrices).
 * ``oracle.nfft_steps`` -- a plain numpy FP64 statement of the windowed
   algorithm the GPU implements (deconvolve, oversampled FFT, window sum),
   used to check the GPU stages one at a time.
@@ -164,6 +166,32 @@ def ndft_grad(fhat: np.ndarray, x: np.ndarray, threads: int | None = None) -> np
     if rc:
         raise RuntimeError(f"oracle_ndft_grad failed ({rc})")
     return out
+
+
+def axis_phases(Nd: int, y) -> np.ndarray:
+    """E[i, k] = exp(-2 pi i k y_i) for frequencies k = -Nd/2 .. Nd/2-1 (array
+    index k + Nd/2): the matrix E^d of Sec. 2.1 in the NFFT sign on the unit
+    period.  The phase k y is reduced mod 1 exactly (the product of an integer
+    below 2^11 and a double is exact in 80-bit long double), then rounded once."""
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    k = frequencies(Nd).astype(np.longdouble)
+    p = y.astype(np.longdouble)[:, None] * k[None, :]
+    r = (p - np.rint(p)).astype(np.float64)
+    return np.cos(2.0 * np.pi * r) - 1j * np.sin(2.0 * np.pi * r)
+
+
+def rgrid_eval(fhat: np.ndarray, y0, y1, y2) -> np.ndarray:
+    """The series at the rectilinear grid y0 x y1 x y2 (Sec. 2.1):
+    F[i0, i1, i2] = sum_k fhat_k exp(-2 pi i (k0 y0[i0] + k1 y1[i1] + k2 y2[i2])),
+    evaluated as the nested sums of Sec. 2.1, one matrix product with E^d per
+    axis: first over k2 (the contiguous axis), then k1, then k0.  FP64."""
+    fhat = np.asarray(fhat, dtype=np.complex128)
+    N0, N1, N2 = _shape3(fhat.shape).tolist()
+    E0, E1, E2 = axis_phases(N0, y0), axis_phases(N1, y1), axis_phases(N2, y2)
+    M0, M1, M2 = E0.shape[0], E1.shape[0], E2.shape[0]
+    t = (fhat.reshape(N0 * N1, N2) @ E2.T).reshape(N0, N1, M2)      # sum over k2
+    t = np.matmul(E1[None, :, :], t)                                 # sum over k1: (N0, M1, M2)
+    return (E0 @ t.reshape(N0, M1 * M2)).reshape(M0, M1, M2)        # sum over k0
 
 
 def frequencies(Nd: int) -> np.ndarray:
