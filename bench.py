@@ -151,6 +151,8 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint / point-gradient / batched / autograd measurements")
+    ap.add_argument("--only", choices=["batched", "autograd"], default=None,
+                    help="run only this extra workload and print its result (profiling runs)")
     return ap.parse_args()
 
 
@@ -210,7 +212,9 @@ def bench_batched(nf, torch, dev, workloads, stream):
     """64 coefficient sets of N in {64, 96, 128}^3 with lognormal point
     counts, each with its three derivative fields: one nfft3_batch_trafo per
     form (one launch per FFT stage and axis length plus one window-sum launch,
-    each over all 256 transforms), timed with HIP events."""
+    each over all transforms of the batch: 256 in FP32, whose derivative
+    fields are spectral; 64 in FP64, whose window sums also form the
+    derivative fields), timed with HIP events."""
     t0 = time.time()
     sets = workloads.batched_sets(64)
     log(f"batched inputs generated in {time.time() - t0:.1f}s")
@@ -235,7 +239,7 @@ def bench_batched(nf, torch, dev, workloads, stream):
         ms = e0.elapsed_time(e1) / reps
         evals = 4 * sum(p.M for p in plans)
         res[form] = {"m": m, "ms_per_batch": ms, "point_evaluations_per_s": evals / (ms * 1e-3)}
-        log(f"batched {form}: {ms:.2f} ms per batch of 256 transforms ({evals / ms * 1e3:.3e} evaluations/s)")
+        log(f"batched {form}: {ms:.2f} ms per batch of 64 sets x 4 fields ({evals / ms * 1e3:.3e} evaluations/s)")
         for p in plans:
             p.close()
         del plans, fh, outs
@@ -289,6 +293,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        stream = torch.cuda.current_stream(dev)
+        if args.only == "batched":
+            res = bench_batched(nf, torch, dev, workloads, stream)
+        else:
+            res = bench_autograd(nf, torch, dev, workloads)
+        print(json.dumps({args.only: res}), flush=True)
+        return
     t0 = time.time()
     N, M = args.N, args.M
     fh, x = workloads.powerlaw_mixed_case(N, M)

@@ -132,7 +132,11 @@ int nfft3_grad_points(nfft3_plan_t p, const void *fhat_dev, const void *G_dev, d
  * (bit 0,1,2 = axis 0,1,2), the derivative field sum_k (-2 pi i k_d) fhat_k
  * exp(-2 pi i k.x) at the plan's points.  out_dev holds (1 + popcount(mask))
  * consecutive blocks of M complex values: the field first, then the
- * derivative fields in axis order. */
+ * derivative fields in axis order.  NFFT3_C128: one grid; the window sums
+ * form the derivative fields through the window derivative (its error stays
+ * within the FP64 accuracy of the transform).  NFFT3_C64: one grid and
+ * transform per field (the spectral multiplier), since the derivative of
+ * the windowed sum amplifies FP32 rounding about n_d-fold. */
 int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int deriv_mask);
 
 /* Batched type-2 evaluation of T independent plans (own N, own points, same
@@ -145,8 +149,10 @@ int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int 
  * one kernel launch per distinct transform length along its axis, the window
  * sums as one launch; each launch covers the work items of every (plan,
  * field) pair in its group, and the results equal the sequential
- * nfft3_trafo_fields results bit for bit.  Each plan keeps one grid per
- * evaluated field, allocated on its first batched call with a given mask.
+ * nfft3_trafo_fields results bit for bit.  NFFT3_C64 plans keep one grid per
+ * evaluated field, allocated on their first batched call with a given mask;
+ * NFFT3_C128 plans use their one grid (derivative fields from the window
+ * derivative, as nfft3_trafo_fields).
  * Work is enqueued on plans[0]'s stream; the call returns after it finished
  * (the launch descriptors are staged from host memory). */
 int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
@@ -161,9 +167,10 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_
  * instead of a library-allocated buffer: about 560 bytes per (plan, field)
  * transform, so roughly 450 transforms per call; a larger batch returns
  * NFFT3_ERR_CAPACITY before any work is enqueued.  Every plan must already
- * hold the grids its fields need: one per plan for deriv_mask = 0, one per
- * evaluated field otherwise (made by an earlier nfft3_batch_trafo call with
- * at least these fields); else NFFT3_ERR_INVALID_ARG.  All calls on one GPU
+ * hold the grids its fields need: NFFT3_C128 plans and deriv_mask = 0 use
+ * the plan's own grid; NFFT3_C64 plans with derivative fields one grid per
+ * evaluated field (made by an earlier nfft3_batch_trafo call with at least
+ * these fields); else NFFT3_ERR_INVALID_ARG.  All calls on one GPU
  * share the array, which keeps the last call's descriptors; calls (of either
  * batch entry point) on one GPU are serialised by a lock in the library,
  * each holding it until its work has finished (the call synchronises before

@@ -411,6 +411,16 @@ int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat, void *out, int mask) {
     if (!p->have_points) return NFFT3_ERR_NO_POINTS;
     if (mask < 0 || mask > 7) return NFFT3_ERR_INVALID_ARG;
     if (!fhat || (p->M > 0 && !out)) return NFFT3_ERR_NULL;
+    if (p->dtype == NFFT3_C128 && mask != 0) {
+        // FP64: the derivative fields through the window derivative, from
+        // the one grid of the field (the window's derivative error stays
+        // within the FP64 gates; in FP32 the rounding of the grid is
+        // amplified ~n_d-fold by the derivative, so FP32 takes the spectral
+        // route below: one grid per field)
+        int rc = launch_grid_forward(p, fhat, p->grid, -1);
+        if (rc) return rc;
+        return launch_fields(p, p->grid, out, mask);
+    }
     char *o = (char *)out;
     for (int field = -1; field < 3; ++field) {
         if (field >= 0 && !(mask & (1 << field))) continue;

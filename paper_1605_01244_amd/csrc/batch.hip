@@ -1,7 +1,10 @@
 // Batched evaluation of many plans (own N, own points; same dtype, sigma, m)
 // and of their derivative fields.
 //
-// Each (plan, field) pair is a transform with four stages: the row pass
+// complex<float>: each (plan, field) pair is a transform (the derivative
+// fields through -2 pi i k_d fhat, one grid each); complex<double>: one
+// transform per plan whose window sums also write the derivative fields
+// (window derivative, as nfft3_trafo_fields).  A transform has four stages: the row pass
 // (deconvolve + zero-pad + FFT along axis 2), the column passes along axes 1
 // and 0, and the window sums.  Each FFT stage runs as one launch per distinct
 // transform length along its axis (a kernel specialised for that length, or
@@ -79,6 +82,17 @@ batch_interp_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int g = batch_find(first, X, blockIdx.x);
     interp_body<T, W, PPT>(xf[ids[g]].ip, blockIdx.x - first[g], smem_raw);
+}
+
+// complex<double> with derivative fields: the field and its derivative fields
+// from the field's one grid (window derivative)
+template <typename T, int W>
+__global__ void __launch_bounds__(kPsThreads) __attribute__((amdgpu_waves_per_eu(2)))
+batch_fields_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids, const int *__restrict__ first,
+                    int X) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int g = batch_find(first, X, blockIdx.x);
+    interp_body_der<T, W, kModeFields>(xf[ids[g]].ip, blockIdx.x - first[g], smem_raw);
 }
 
 // one launch of a stage over one group of transforms
@@ -174,9 +188,14 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
         ~Restore() { (void)hipSetDevice(dev); }
     } restore{cur_dev};
     if (cur_dev != dev) NFFT3_HIP_TRY(hipSetDevice(dev));
+    // complex<double>: derivative fields through the window derivative from
+    // the field's grid (as nfft3_trafo_fields); complex<float>: one grid and
+    // transform per field (spectral derivative)
+    constexpr bool kDouble = sizeof(T) == 8;
+    const bool der_fields = kDouble && mask != 0;
     std::vector<int> fields = {-1};
     for (int d = 0; d < 3; ++d)
-        if (mask & (1 << d)) fields.push_back(d);
+        if (!der_fields && (mask & (1 << d))) fields.push_back(d);
     const int F = (int)fields.size();
     const int X = T_ * F;
     std::vector<BatchXform> xf((size_t)X);
@@ -205,6 +224,10 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             if (!interp_layout_ok(p, b.ip)) return NFFT3_ERR_INVALID_ARG;
             b.ip.grid = grid;
             b.ip.out = (char *)out[t] + (size_t)f * p->M * p->elt;
+            if (der_fields) {
+                b.ip.fmask = mask;
+                b.ip.fstride = p->M;
+            }
             b.gx1 = col_grid_x(b.c1);
             b.gx0 = col_grid_x(b.c0);
             b.ntile[0] = (int)row_blocks(p, b.rows);
@@ -296,6 +319,13 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             if (stage < 3) {
                 launch_group_fft<T>(g, dxf, dids, dfirst, stream);
                 NFFT3_LAUNCH_CHECK("batch_fft_kernel");
+            } else if (der_fields) {
+                if constexpr (kDouble) {
+                    allow_lds((const void *)batch_fields_kernel<T, W>, g.lds);
+                    hipLaunchKernelGGL((batch_fields_kernel<T, W>), dim3((unsigned)g.total), dim3(kPsThreads),
+                                       g.lds, stream, dxf, dids, dfirst, (int)g.ids.size());
+                    NFFT3_LAUNCH_CHECK("batch_fields_kernel");
+                }
             } else {
                 allow_lds((const void *)batch_interp_kernel<T, W, PPT>, g.lds);
                 hipLaunchKernelGGL((batch_interp_kernel<T, W, PPT>), dim3((unsigned)g.total), dim3(kPsThreads),

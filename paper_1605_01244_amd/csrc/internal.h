@@ -215,6 +215,8 @@ int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equ
 // window sums and their point derivative (interp.hip)
 int launch_interp(nfft3_plan_impl *p, const void *grid, void *f);
 int launch_grad(nfft3_plan_impl *p, const void *grid, const void *G, double *grad_x);
+// complex<double> only: the field and the derivative fields of mask from one grid
+int launch_fields(nfft3_plan_impl *p, const void *grid, void *out, int mask);
 // spreading, the adjoint window step, and the grid fill (spread.hip)
 int launch_spread(nfft3_plan_impl *p, const void *f, void *grid);
 int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);

@@ -1,6 +1,8 @@
 // Stage (c) of the windowed evaluation and its derivative in the points:
 //   interp : f_j      = sum_{r in {-m+1..m}^3} g[(u_j + r) mod n] prod_d w_d(r_d)
 //   grad   : d f_j/d x_{j,d} = n_d sum_r g[...] w_d'(r_d) prod_{e != d} w_e(r_e)
+//            (contracted with the cotangent G_j for the point gradient, or
+//            written out as the derivative fields)
 // (the adjoint, spreading, is in spread.hip)
 // with u_j = floor(n x_j) and w_d(r) = phi((n x_j)_d - u_d - r)/phi(0) from the
 // per-offset window polynomials in the cell fraction (see api.hip).  Cell and
@@ -29,19 +31,23 @@ __global__ void __launch_bounds__(kPsThreads) interp_ps_kernel(PSArgs a) {
     interp_body<T, W, PPT>(a, xcd_item(blockIdx.x, gridDim.x), smem_raw);
 }
 
-// ------------------------------------------------------------- grad ----
-// The interp body in its derivative mode (rotated, conflict-free reads), one
+// ------------------------------------------------------- grad, fields ----
+// The interp body in its derivative modes (rotated, conflict-free reads), one
 // point per thread: items of more points are taken 256 at a time.
 template <typename T, int W>
 __global__ void __launch_bounds__(kPsThreads) __attribute__((amdgpu_waves_per_eu(2)))
 grad_ps_kernel(PSArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int idx = xcd_item(blockIdx.x, gridDim.x);
-    const int4 item = a.items[idx];
-    for (int lo = item.y; lo < item.z; lo += kPsThreads) {
-        __syncthreads();
-        interp_range<T, W, 1, true>(a, idx, make_int4(item.x, lo, min(item.z, lo + kPsThreads), 0), smem_raw);
-    }
+    interp_body_der<T, W, kModeGrad>(a, xcd_item(blockIdx.x, gridDim.x), smem_raw);
+}
+
+// the field and its derivative fields from one grid (complex<double>: the
+// window derivative meets the FP64 gates; see launch_fields)
+template <typename T, int W>
+__global__ void __launch_bounds__(kPsThreads) __attribute__((amdgpu_waves_per_eu(2)))
+fields_ps_kernel(PSArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    interp_body_der<T, W, kModeFields>(a, xcd_item(blockIdx.x, gridDim.x), smem_raw);
 }
 
 // ------------------------------------------------------------ dispatch ----
@@ -82,6 +88,28 @@ static int grad_w(nfft3_plan_impl *p, const void *grid, const void *G, double *g
     hipLaunchKernelGGL((grad_ps_kernel<T, W>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds, p->stream, a);
     NFFT3_LAUNCH_CHECK("grad_ps_kernel");
     return NFFT3_OK;
+}
+
+template <typename T, int W>
+static int fields_w(nfft3_plan_impl *p, const void *grid, void *out, int mask) {
+    if (p->M == 0 || p->sub.count == 0) return NFFT3_OK;
+    PSArgs a = interp_args(p);
+    if (!interp_layout_ok(p, a)) return NFFT3_ERR_INVALID_ARG;
+    a.grid = grid;
+    a.out = out;
+    a.fmask = mask;
+    a.fstride = p->M;
+    const size_t lds = interp_lds(p, a);
+    allow_lds((const void *)fields_ps_kernel<T, W>, lds);
+    hipLaunchKernelGGL((fields_ps_kernel<T, W>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds, p->stream,
+                       a);
+    NFFT3_LAUNCH_CHECK("fields_ps_kernel");
+    return NFFT3_OK;
+}
+
+int launch_fields(nfft3_plan_impl *p, const void *grid, void *out, int mask) {
+    if (p->dtype != NFFT3_C128) return NFFT3_ERR_DTYPE;
+    NFFT3_DISPATCH_M(fields_w, double, grid, out, mask)
 }
 
 int launch_interp(nfft3_plan_impl *p, const void *grid, void *f) {

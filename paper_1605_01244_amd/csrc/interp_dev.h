@@ -121,7 +121,14 @@ struct PSArgs {
     int By, Bx, ntx;
     int pxp;                // interp: LDS row stride of a staged plane (elements); 0 = unpadded
     int qinv;               // interp: inverse of (row stride in 16-B units / D) mod 16/D
+    int fmask;              // fields: derivative axes written after the field (bit d = axis d)
+    int64_t fstride;        // fields: elements between consecutive output blocks (M)
 };
+
+// What the window-sum body computes at each point.
+constexpr int kModeValue = 0;    // f_j
+constexpr int kModeGrad = 1;     // Re(conj(G_j) d f_j/d x_{j,d}), d = 0, 1, 2
+constexpr int kModeFields = 2;   // f_j and the derivative fields d f_j/d x_{j,d} of fmask
 
 // Per-workgroup setup shared by the three kernels.
 struct PSItem {
@@ -324,19 +331,21 @@ __device__ __forceinline__ bool interp_walk_down(int item, int nplanes, int W) {
 
 // Point slot k of thread t is sorted index item.y + k*256 + t: each slot's
 // wavefronts hold z-adjacent points, so they are active on the same planes.
-// GRAD: instead of the values, the derivative sums of the point gradient
-// (grad_x[j, d] = n_d Re(conj(G_j) D_d) with D_0 = sum w0' w1 w2 g,
-// D_1 = sum w0 w1' w2 g, D_2 = sum w0 w1 w2' g): the y derivative weights
-// rotate with the y weights and the x derivative weights are shifted like
-// the x weights, so the reads are the same.
+// Derivative modes (kModeGrad, kModeFields) also form the derivative sums
+// D_0 = sum w0' w1 w2 g, D_1 = sum w0 w1' w2 g, D_2 = sum w0 w1 w2' g (so
+// d f_j / d x_{j,d} = n_d D_d): the y derivative weights rotate with the y
+// weights and the x derivative weights are shifted like the x weights, so the
+// reads are the same.  kModeGrad writes grad_x[j, d] = n_d Re(conj(G_j) D_d),
+// kModeFields the field and the derivative fields n_d D_d of a.fmask.
 
-template <typename T, int W, int PPT, bool GRAD>
+template <typename T, int W, int PPT, int MODE>
 __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, const int4 item,
                                              unsigned char *smem_raw) {
     constexpr int m = W / 2;
     using U = typename LdsUnit<T>::type;
     constexpr int EPU = LdsUnit<T>::EPU;
     constexpr bool TWIN = EPU == 2;                // complex<float>: aligned + shifted copy
+    constexpr bool GRAD = MODE != kModeValue;      // derivative sums
     constexpr int NR = EPU == 1 ? W : W / 2;       // units read per stencil row
     constexpr int NW = NR * EPU;                   // column weights per row
     constexpr int D = 16 / cgcd(W, 16);            // cosets of bank groups
@@ -365,6 +374,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
     T w1[PPT][W], wt[PPT][NW];
     T d1[PPT][WG], dt[PPT][NWG];                   // GRAD: derivative weights
     T f0[PPT], ar[PPT], ai[PPT];
+    T vr[PPT], vi[PPT];                            // kModeFields: the value
     T g1r[PPT], g1i[PPT], g2r[PPT], g2i[PPT];      // GRAD: D_1, D_2 (ar, ai hold D_0)
     int zlo[PPT], ub0[PPT], ub1[PPT], tt[PPT];
 #pragma unroll
@@ -373,6 +383,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
         const bool active = pk < item.z;
         ar[k] = 0;
         ai[k] = 0;
+        vr[k] = vi[k] = 0;
         g1r[k] = g1i[k] = g2r[k] = g2i[k] = 0;
         zlo[k] = -4 * W;     // never active
         f0[k] = 0;
@@ -554,6 +565,10 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
                     g1i[k] += w0 * ui;
                     g2r[k] += w0 * vr2;   // D_2
                     g2i[k] += w0 * vi2;
+                    if constexpr (MODE == kModeFields) {
+                        vr[k] += w0 * sr;
+                        vi[k] += w0 * si;
+                    }
                 } else {
                     ar[k] += w0 * sr;
                     ai[k] += w0 * si;
@@ -578,7 +593,14 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
         const int pk = item.y + k * kPsThreads + threadIdx.x;
         if (pk >= item.z) continue;
         const int pj = a.perm[pk];
-        if constexpr (GRAD) {
+        if constexpr (MODE == kModeFields) {
+            c_t<T> *o = (c_t<T> *)a.out;
+            o[pj] = cmk<T>(vr[k], vi[k]);
+            int64_t at = a.fstride + pj;
+            if (a.fmask & 1) { o[at] = cmk<T>((T)a.n0 * ar[k], (T)a.n0 * ai[k]); at += a.fstride; }
+            if (a.fmask & 2) { o[at] = cmk<T>((T)a.n1 * g1r[k], (T)a.n1 * g1i[k]); at += a.fstride; }
+            if (a.fmask & 4) o[at] = cmk<T>((T)a.n2 * g2r[k], (T)a.n2 * g2i[k]);
+        } else if constexpr (GRAD) {
             // Re(conj(G) D) = G.x D.x + G.y D.y, times n_d (dt/dx)
             const c_t<T> g = ((const c_t<T> *)a.vals)[pj];
             double *gx = (double *)a.out + 3 * (int64_t)pj;
@@ -592,9 +614,20 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
 }
 
 
-template <typename T, int W, int PPT, bool GRAD = false>
+template <typename T, int W, int PPT>
 __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, unsigned char *smem_raw) {
-    interp_range<T, W, PPT, GRAD>(a, item_index, a.items[item_index], smem_raw);
+    interp_range<T, W, PPT, kModeValue>(a, item_index, a.items[item_index], smem_raw);
+}
+
+// Derivative modes: one point per thread (to stay within two waves per SIMD
+// without spills at m = 8); items of more points are taken 256 at a time.
+template <typename T, int W, int MODE>
+__device__ __forceinline__ void interp_body_der(const PSArgs &a, int item_index, unsigned char *smem_raw) {
+    const int4 item = a.items[item_index];
+    for (int lo = item.y; lo < item.z; lo += kPsThreads) {
+        __syncthreads();
+        interp_range<T, W, 1, MODE>(a, item_index, make_int4(item.x, lo, min(item.z, lo + kPsThreads), 0), smem_raw);
+    }
 }
 
 inline PSArgs ps_args(const nfft3_plan_impl *p) {
@@ -616,6 +649,8 @@ inline PSArgs ps_args(const nfft3_plan_impl *p) {
     a.ntx = p->bins.ntx;
     a.pxp = 0;
     a.qinv = 0;
+    a.fmask = 0;
+    a.fstride = 0;
     return a;
 }
 
