@@ -147,6 +147,9 @@ static void free_points(nfft3_plan_impl *p) {
     (void)hipFree(p->perm); p->perm = nullptr;
     (void)hipFree(p->bin_of); p->bin_of = nullptr;
     (void)hipFree(p->rank); p->rank = nullptr;
+    (void)hipFree(p->tx); p->tx = nullptr;
+    (void)hipFree(p->tperm); p->tperm = nullptr;
+    (void)hipFree(p->tz); p->tz = nullptr;
     p->cap_pts = 0;
 }
 
@@ -156,6 +159,9 @@ static void free_bins(nfft3_plan_impl *p) {
     (void)hipFree(p->bins.scratch); p->bins.scratch = nullptr;
     (void)hipFree(p->bins.tile_items); p->bins.tile_items = nullptr;
     (void)hipFree(p->bins.tile_item_off); p->bins.tile_item_off = nullptr;
+    (void)hipFree(p->bins.tile_counts); p->bins.tile_counts = nullptr;
+    (void)hipFree(p->bins.tile_start); p->bins.tile_start = nullptr;
+    (void)hipFree(p->bins.chunk_start); p->bins.chunk_start = nullptr;
 }
 static void free_plan(nfft3_plan_impl *p) {
     if (!p) return;
@@ -263,15 +269,19 @@ static int alloc_bins(nfft3_plan_impl *p, int T) {
     p->bins.ntx = (int)((p->n[2] + p->bins.Bx - 1) / p->bins.Bx);
     const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
     const int64_t nb = ntiles * p->n[0];
-    const int64_t nc = nb * kBinCopies;
-    // counter indices (bin kBinCopies + copy) and sorted positions are int
-    if (nc + 1 > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
     p->bins.nbins = nb;
+    p->bins.copies = two_level_sort(p) ? 1 : kBinCopies;
+    const int64_t nc = nb * p->bins.copies;
+    // counter indices (bin copies + copy) and sorted positions are int
+    if (nc + 1 > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
     NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nc));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nc + 1)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nc / 1024 + 2)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * ntiles));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (ntiles + 1)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_counts, sizeof(int) * ntiles));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_start, sizeof(int) * (ntiles + 1)));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.chunk_start, sizeof(int) * (ntiles + 1)));
     return NFFT3_OK;
 }
 
@@ -374,6 +384,9 @@ int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x) {
         NFFT3_HIP_TRY(hipMalloc(&p->perm, sizeof(int) * M));
         NFFT3_HIP_TRY(hipMalloc(&p->bin_of, sizeof(int) * M));
         NFFT3_HIP_TRY(hipMalloc(&p->rank, sizeof(int) * M));
+        NFFT3_HIP_TRY(hipMalloc(&p->tx, sizeof(double) * 3 * M));
+        NFFT3_HIP_TRY(hipMalloc(&p->tperm, sizeof(int) * M));
+        NFFT3_HIP_TRY(hipMalloc(&p->tz, sizeof(int) * M));
         p->cap_pts = M;
     }
     int rc = launch_set_points(p, M, x);

@@ -129,9 +129,13 @@ struct Bins {
     int By = 32, Bx = 32;     // tile size in cells (y, x)
     int nty = 0, ntx = 0;     // tiles per axis
     int64_t nbins = 0;        // nty * ntx * n0
-    int *counts = nullptr;    // point counts, kBinCopies counters per bin (device)
-    int *offsets = nullptr;   // exclusive scan of counts, nbins kBinCopies + 1 entries (device)
+    int copies = 1;           // counters per bin: 1 (two-level sort) or kBinCopies (single-level)
+    int *counts = nullptr;    // point counts, `copies` counters per bin (device)
+    int *offsets = nullptr;   // exclusive scan of counts, nbins copies + 1 entries (device)
     int *scratch = nullptr;   // block sums of the scans
+    int *tile_counts = nullptr;     // two-level sort: points (then level-2 chunks) per tile
+    int *tile_start = nullptr;      // exclusive scan of the points per tile, ntiles + 1
+    int *chunk_start = nullptr;     // exclusive scan of the chunks per tile, ntiles + 1
     int *tile_items = nullptr;      // items per tile (device)
     int *tile_item_off = nullptr;   // exclusive scan, ntiles + 1 entries (device)
 };
@@ -167,8 +171,11 @@ struct nfft3_plan_impl {
     int64_t cap_pts = 0;
     double *xs = nullptr;     // sorted folded points, (M,3)
     int *perm = nullptr;      // sorted position -> caller index
-    int *bin_of = nullptr;    // per caller index: bin id (scratch)
-    int *rank = nullptr;      // per caller index: rank inside bin (scratch)
+    int *bin_of = nullptr;    // per caller index: bin id / rank in tile (scratch)
+    int *rank = nullptr;      // rank inside bin (scratch)
+    double *tx = nullptr;     // two-level sort: folded points in tile order (scratch, (M,3))
+    int *tperm = nullptr;     // two-level sort: caller index in tile order (scratch)
+    int *tz = nullptr;        // two-level sort: z-cell in tile order (scratch)
     int *flag = nullptr;      // device status word (non-finite points)
     Bins bins;
     int tile_req = kMaxTile;  // requested tile edge (By, Bx may be smaller)
@@ -210,6 +217,8 @@ int launch_grid_forward(nfft3_plan_impl *p, const void *fhat, void *grid, int de
 int launch_grid_adjoint(nfft3_plan_impl *p, void *grid, void *fhat);
 // points (points.hip)
 int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x);
+// whether set_points uses the two-level (LDS) sort for the plan's tiling
+bool two_level_sort(const nfft3_plan_impl *p);
 // *equal = 1 when the sorted points are those of x (no new sort needed)
 int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equal);
 // window sums and their point derivative (interp.hip)
