@@ -151,7 +151,7 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint / point-gradient / batched / autograd measurements")
-    ap.add_argument("--only", choices=["batched", "autograd"], default=None,
+    ap.add_argument("--only", choices=["batched", "autograd", "rectilinear"], default=None,
                     help="run only this extra workload and print its result (profiling runs)")
     return ap.parse_args()
 
@@ -247,6 +247,38 @@ def bench_batched(nf, torch, dev, workloads, stream):
     return res
 
 
+def bench_rgrid(nf, torch, dev, workloads, stream):
+    """Evaluation at a rectilinear grid (Sec. 2.1) on the matrix cores: the
+    paper's 64^3 coefficients at a 64^3 grid, and 256^3 power-law
+    coefficients at a nonuniform 321^3 grid; per form the median event time
+    of nfft3_rgrid_eval and its rate against the dense MFMA peak of its dtype
+    (algorithmic flops 8 (N0 N1 N2 M2 + N0 N1 M1 M2 + N0 M0 M1 M2))."""
+    res = {}
+    r = np.random.default_rng(16)
+    for name, N, M in (("64^3->64^3", (64, 64, 64), (64, 64, 64)), ("256^3->321^3", (256, 256, 256), (321, 321, 321))):
+        fh = workloads.powerlaw_coeffs(N, 301) if N[0] == 256 else (
+            np.random.default_rng(13).standard_normal(N) + 1j * np.random.default_rng(14).standard_normal(N))
+        ys = [torch.from_numpy(np.sort(r.uniform(-0.5, 0.5, size=m))).to(dev) for m in M]
+        flops = 8.0 * (N[0] * N[1] * N[2] * M[2] + N[0] * N[1] * M[1] * M[2] + N[0] * M[0] * M[1] * M[2])
+        entry = {"N": list(N), "M": list(M), "flops": flops}
+        for form, dt, peak in (("fp64", torch.complex128, FP64_PEAK_TFLOPS), ("fp32", torch.complex64, FP32_PEAK_TFLOPS)):
+            g = nf.RectGrid(N, M, dtype=dt, device=dev)
+            g.set_axes(*ys)
+            fd = torch.from_numpy(fh).to(dev).to(dt)
+            out = torch.empty(M, dtype=dt, device=dev)
+            g.eval(fd, out=out)
+            ms = median(event_times(torch, stream, lambda: g.eval(fd, out=out), 10)[0])
+            tfs = flops / (ms * 1e-3) / 1e12
+            entry[form] = {"ms": ms, "tflops": tfs, "peak_tflops": peak, "frac": tfs / peak,
+                           "points_per_s": M[0] * M[1] * M[2] / (ms * 1e-3)}
+            log(f"rectilinear {name} {form}: {ms:.3f} ms, {tfs:.1f} TFLOP/s ({tfs / peak:.2f} of MFMA peak)")
+            g.close()
+            del out, fd
+        res[name] = entry
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_autograd(nf, torch, dev, workloads):
     """Differentiation form: N = 128^3, M = 1e6 clustered points; forward
     (set_points + trafo) and backward (adjoint + point gradient) of
@@ -297,6 +329,8 @@ def main():
         stream = torch.cuda.current_stream(dev)
         if args.only == "batched":
             res = bench_batched(nf, torch, dev, workloads, stream)
+        elif args.only == "rectilinear":
+            res = bench_rgrid(nf, torch, dev, workloads, stream)
         else:
             res = bench_autograd(nf, torch, dev, workloads)
         print(json.dumps({args.only: res}), flush=True)
@@ -380,6 +414,7 @@ def main():
         torch.cuda.empty_cache()
         extras["batched"] = bench_batched(nf, torch, dev, workloads, stream)
         extras["autograd"] = bench_autograd(nf, torch, dev, workloads)
+        extras["rectilinear"] = bench_rgrid(nf, torch, dev, workloads, stream)
 
     # CPU baseline = the oracle on the seeded sample (also the error reference)
     cpu = None

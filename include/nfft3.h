@@ -179,6 +179,36 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_
 int nfft3_batch_trafo_noalloc(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
                               void *const *out_dev, int deriv_mask);
 
+/* ---- Evaluation at a rectilinear grid (Sec. 2.1) ---------------------------
+ * The series at every point of a grid y0 x y1 x y2 with arbitrary (not
+ * necessarily equispaced) coordinates per axis:
+ *
+ *     F[i0][i1][i2] = sum_{k in I_N} fhat_k exp(-2 pi i (k0 y0[i0] + k1 y1[i1] + k2 y2[i2]))
+ *
+ * (the NFFT sign on the unit period, as nfft3_trafo; the paper's E^d matrices
+ * and nested sums of Sec. 2.1).  Exact up to rounding (no window): three
+ * dense complex matrix products, one per axis, on the matrix cores (FP64 or
+ * FP32 MFMA), with the E^d tables formed on the device from the coordinates.
+ * Cost 8 (N0 N1 N2 M2 + N0 N1 M1 M2 + N0 M0 M1 M2) real flops. */
+typedef struct nfft3_rgrid_s *nfft3_rgrid_t;
+
+/* Plan for N[3] coefficients (N_d even, 2 <= N_d <= 16384) and M[3] grid
+ * points per axis (1 <= M_d <= 2^20), dtype NFFT3_C64 / NFFT3_C128, on the
+ * current device and the given stream (NULL = default).  Allocates the E^d
+ * tables and two intermediates of N0 N1 M2 and N0 M1 M2 complex values. */
+int nfft3_rgrid_plan(nfft3_rgrid_t *out, const int64_t N[3], const int64_t M[3], int dtype, void *stream);
+int nfft3_rgrid_set_stream(nfft3_rgrid_t g, void *stream);
+/* Grid coordinates: y_d_dev holds M_d FP64 values (device; any finite
+ * reals, the series being 1-periodic).  Forms the E^d tables; synchronises
+ * once to report NFFT3_ERR_NONFINITE. */
+int nfft3_rgrid_set_axes(nfft3_rgrid_t g, const double *y0_dev, const double *y1_dev, const double *y2_dev);
+/* out_dev[i0][i1][i2] (C order, M0 x M1 x M2 complex) = F at the grid;
+ * fhat_dev: C-order (N0, N1, N2) complex, index i_d <-> k_d = i_d - N_d/2.
+ * NFFT3_ERR_NO_POINTS before nfft3_rgrid_set_axes.  Does not synchronise. */
+int nfft3_rgrid_eval(nfft3_rgrid_t g, const void *fhat_dev, void *out_dev);
+/* Release the plan (NULL is a no-op). */
+int nfft3_rgrid_destroy(nfft3_rgrid_t g);
+
 /* ---- Tuning of the point binning (not in the paper; the window sums of
  * Sec. 2.2.1 at the plan's points are computed the same way for every
  * setting, only faster or slower) ---------------------------------------- */

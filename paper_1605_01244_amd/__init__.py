@@ -26,7 +26,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 from ._lib import NFFT3_C64, NFFT3_C128, NFFT3Error, check, lib
 
-__all__ = ["Plan", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error"]
+__all__ = ["Plan", "RectGrid", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error"]
 
 _DT = {torch.complex64: NFFT3_C64, torch.complex128: NFFT3_C128}
 
@@ -233,6 +233,69 @@ class Plan:
         g = g.contiguous()
         self._bind_stream()
         check(lib.nfft3_grid_copy(self._h, _ptr(g), 1), "nfft3_grid_copy")
+
+
+class RectGrid:
+    """The series at a rectilinear grid y0 x y1 x y2 (Sec. 2.1), exact up to
+    rounding: F[i0, i1, i2] = sum_k fhat_k exp(-2 pi i (k0 y0[i0] + k1 y1[i1]
+    + k2 y2[i2])), computed as three complex matrix products on the matrix
+    cores.  N: coefficient sizes; M: grid points per axis."""
+
+    def __init__(self, N: Sequence[int], M: Sequence[int], dtype: torch.dtype = torch.complex128, device=None):
+        if dtype not in _DT:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("RectGrid needs a GPU device")
+        self.N = tuple(int(v) for v in N)
+        self.M = tuple(int(v) for v in M)
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(lib.nfft3_rgrid_plan(ctypes.byref(self._h), (ctypes.c_int64 * 3)(*self.N),
+                                       (ctypes.c_int64 * 3)(*self.M), _DT[dtype], ctypes.c_void_p(stream)),
+                  "nfft3_rgrid_plan")
+        self._axes = None
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib.nfft3_rgrid_set_stream(self._h, ctypes.c_void_p(s)), "nfft3_rgrid_set_stream")
+
+    def set_axes(self, y0: torch.Tensor, y1: torch.Tensor, y2: torch.Tensor) -> None:
+        """Grid coordinates per axis: float64 vectors of M_d values on the device."""
+        ys = []
+        for d, y in enumerate((y0, y1, y2)):
+            if y.dtype != torch.float64 or y.device != self.device or y.numel() != self.M[d]:
+                raise ValueError(f"y{d} must be {self.M[d]} float64 values on {self.device}")
+            ys.append(y.contiguous())
+        self._bind_stream()
+        check(lib.nfft3_rgrid_set_axes(self._h, *[_ptr(y) for y in ys]), "nfft3_rgrid_set_axes")
+        self._axes = ys
+
+    def eval(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if tuple(fhat.shape) != self.N or fhat.dtype != self.dtype or fhat.device != self.device:
+            raise ValueError(f"coefficients must be {self.N} {self.dtype} on {self.device}")
+        fhat = fhat.contiguous()
+        if out is None:
+            out = torch.empty(self.M, dtype=self.dtype, device=self.device)
+        elif tuple(out.shape) != self.M or out.dtype != self.dtype or out.device != self.device:
+            raise ValueError(f"out must be {self.M} {self.dtype} on {self.device}")
+        Plan._out(out)
+        self._bind_stream()
+        check(lib.nfft3_rgrid_eval(self._h, _ptr(fhat), _ptr(out)), "nfft3_rgrid_eval")
+        return out
+
+    def close(self):
+        if self._h:
+            lib.nfft3_rgrid_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0,

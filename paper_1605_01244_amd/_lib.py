@@ -58,6 +58,11 @@ def _load() -> ctypes.CDLL:
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),
         "nfft3_batch_trafo": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
         "nfft3_batch_trafo_noalloc": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
+        "nfft3_rgrid_plan": ([ctypes.POINTER(vp), i64p, i64p, ci, vp], ci),
+        "nfft3_rgrid_set_stream": ([vp, vp], ci),
+        "nfft3_rgrid_set_axes": ([vp, vp, vp, vp], ci),
+        "nfft3_rgrid_eval": ([vp, vp, vp], ci),
+        "nfft3_rgrid_destroy": ([vp], ci),
         "nfft3_set_tuning": ([vp, ci, ci], ci),
         "nfft3_get_tuning": ([vp, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
         "nfft3_autotune": ([vp, i64, vp, vp, vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),

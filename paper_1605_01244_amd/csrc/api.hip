@@ -513,6 +513,87 @@ const char *nfft3_strerror(int code) {
 
 const char *nfft3_last_hip_error(void) { return g_last_hip.c_str(); }
 
+// ---- evaluation at a rectilinear grid (Sec. 2.1) ----------------------------
+
+static void free_rgrid(nfft3_rgrid_impl *g) {
+    for (int d = 0; d < 3; ++d) { (void)hipFree(g->E[d]); g->E[d] = nullptr; }
+    (void)hipFree(g->t1); g->t1 = nullptr;
+    (void)hipFree(g->t2); g->t2 = nullptr;
+    (void)hipFree(g->flag); g->flag = nullptr;
+}
+
+int nfft3_rgrid_plan(nfft3_rgrid_t *out, const int64_t N[3], const int64_t M[3], int dtype, void *stream) {
+    if (!out) return NFFT3_ERR_NULL;
+    *out = nullptr;
+    if (!N || !M) return NFFT3_ERR_NULL;
+    if (dtype != NFFT3_C64 && dtype != NFFT3_C128) return NFFT3_ERR_DTYPE;
+    for (int d = 0; d < 3; ++d) {
+        if (N[d] < 2 || N[d] % 2 || N[d] > kRgridMaxN) return NFFT3_ERR_INVALID_ARG;
+        if (M[d] < 1 || M[d] > kRgridMaxM) return NFFT3_ERR_INVALID_ARG;
+    }
+    auto *g = new (std::nothrow) nfft3_rgrid_s();
+    if (!g) return NFFT3_ERR_OOM;
+    g->dtype = dtype;
+    g->elt = dtype == NFFT3_C128 ? 16 : 8;
+    g->stream = (hipStream_t)stream;
+    for (int d = 0; d < 3; ++d) { g->N[d] = N[d]; g->M[d] = M[d]; }
+    int rc = NFFT3_OK;
+    auto fail = [&](int code) { free_rgrid(g); delete g; return code; };
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) { set_hip_error(e, "hipGetDevice"); return fail(NFFT3_ERR_HIP); }
+    const size_t sizes[5] = {(size_t)(M[0] * N[0]), (size_t)(M[1] * N[1]), (size_t)(N[2] * M[2]),
+                             (size_t)(N[0] * N[1] * M[2]), (size_t)(N[0] * M[1] * M[2])};
+    void **dst[5] = {&g->E[0], &g->E[1], &g->E[2], &g->t1, &g->t2};
+    for (int i = 0; i < 5; ++i) {
+        e = hipMalloc(dst[i], sizes[i] * g->elt);
+        if (e != hipSuccess) {
+            set_hip_error(e, "hipMalloc (rectilinear grid)");
+            return fail(e == hipErrorOutOfMemory ? NFFT3_ERR_OOM : NFFT3_ERR_HIP);
+        }
+    }
+    e = hipMalloc(&g->flag, 64);
+    if (e != hipSuccess) { set_hip_error(e, "hipMalloc (flag)"); return fail(NFFT3_ERR_OOM); }
+    (void)rc;
+    *out = g;
+    return NFFT3_OK;
+}
+
+int nfft3_rgrid_set_stream(nfft3_rgrid_t g, void *stream) {
+    if (!g) return NFFT3_ERR_NULL;
+    g->stream = (hipStream_t)stream;
+    return NFFT3_OK;
+}
+
+int nfft3_rgrid_set_axes(nfft3_rgrid_t g, const double *y0, const double *y1, const double *y2) {
+    if (!g) return NFFT3_ERR_NULL;
+    if (!y0 || !y1 || !y2) return NFFT3_ERR_NULL;
+    g->have_axes = false;
+    const double *y[3] = {y0, y1, y2};
+    int rc = launch_rgrid_axes(g, y);
+    if (rc) return rc;
+    int flag = 0;
+    NFFT3_HIP_TRY(hipMemcpyAsync(&flag, g->flag, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    NFFT3_HIP_TRY(hipStreamSynchronize(g->stream));
+    if (flag & 1) return NFFT3_ERR_NONFINITE;
+    g->have_axes = true;
+    return NFFT3_OK;
+}
+
+int nfft3_rgrid_eval(nfft3_rgrid_t g, const void *fhat, void *out) {
+    if (!g) return NFFT3_ERR_NULL;
+    if (!g->have_axes) return NFFT3_ERR_NO_POINTS;
+    if (!fhat || !out) return NFFT3_ERR_NULL;
+    return launch_rgrid_eval(g, fhat, out);
+}
+
+int nfft3_rgrid_destroy(nfft3_rgrid_t g) {
+    if (!g) return NFFT3_OK;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    free_rgrid(g);
+    delete g;
+    return NFFT3_OK;
+}
+
 int nfft3_set_tuning(nfft3_plan_t p, int tile, int items) {
     if (!p) return NFFT3_ERR_NULL;
     if (tile != 0 && (tile < 8 || tile > kMaxTile || tile % 4 != 0)) return NFFT3_ERR_INVALID_ARG;

@@ -183,6 +183,23 @@ struct nfft3_plan_impl {
     int64_t epoch = 0;        // bumps at every set_points
 };
 
+// Evaluation at a rectilinear grid (Sec. 2.1): three complex matrix products.
+constexpr int64_t kRgridMaxN = 1 << 14;   // coefficients per axis
+constexpr int64_t kRgridMaxM = 1 << 20;   // grid points per axis
+struct nfft3_rgrid_impl {
+    int dtype = NFFT3_C128;
+    int64_t N[3] = {0, 0, 0};   // coefficients
+    int64_t M[3] = {0, 0, 0};   // grid points per axis
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t elt = 16;
+    void *E[3] = {nullptr, nullptr, nullptr};   // E0 (M0 x N0), E1 (M1 x N1), E2^T (N2 x M2)
+    void *t1 = nullptr;         // N0 N1 M2 (after the sum over k2)
+    void *t2 = nullptr;         // N0 M1 M2 (after the sum over k1)
+    int *flag = nullptr;        // device status word (non-finite coordinates)
+    bool have_axes = false;
+};
+
 // Raise a kernel's dynamic-LDS limit above the 64 KiB default when needed.
 void allow_lds(const void *kernel, size_t bytes);
 
@@ -233,6 +250,11 @@ int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);
 int launch_batch(int T, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out,
                  int deriv_mask, bool noalloc);
 
+// rectilinear grid (rgrid.hip)
+int launch_rgrid_axes(nfft3_rgrid_impl *g, const double *const y[3]);
+int launch_rgrid_eval(nfft3_rgrid_impl *g, const void *fhat, void *out);
+
 }  // namespace nfft3
 
 struct nfft3_plan_s : nfft3::nfft3_plan_impl {};
+struct nfft3_rgrid_s : nfft3::nfft3_rgrid_impl {};

@@ -1,0 +1,258 @@
+// Evaluation of the series at a rectilinear grid (Sec. 2.1):
+//
+//   F[i0, i1, i2] = sum_k fhat_k e0[i0, k0] e1[i1, k1] e2[i2, k2],
+//   e_d[i, k] = exp(-2 pi i k y_d[i]),  k = -N_d/2 .. N_d/2 - 1,
+//
+// in the NFFT sign on the unit period (the convention of nfft3_trafo).  As in
+// Sec. 2.1 the nested sums are three dense complex matrix products, one per
+// axis, the contiguous axis first:
+//
+//   t1[(k0, k1), i2] = sum_k2 fhat[(k0, k1), k2] e2^T[k2, i2]     (N0 N1 x N2) (N2 x M2)
+//   t2[k0][i1, i2]   = sum_k1 e1[i1, k1] t1[k0][k1, i2]           N0 x (M1 x N1) (N1 x M2)
+//   F[i0, (i1, i2)]  = sum_k0 e0[i0, k0] t2[k0, (i1, i2)]         (M0 x N0) (N0 x M1 M2)
+//
+// All three are row-major C = A B products, so one kernel serves them: a
+// complex GEMM on the matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32)
+// with each complex product taken as four real ones.  The E^d tables are formed
+// on the device from the coordinates with the phase k y reduced mod 1 in one
+// fused multiply-add (rounded once), so their error does not grow with |k y|.
+#include "internal.h"
+
+namespace nfft3 {
+
+typedef double dx4_t __attribute__((ext_vector_type(4)));
+typedef float fx4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Operand layout (both): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.
+// Result element r of lane l holds D[row(l / 16, r)][l % 16]; the row order
+// differs between the two (checked on gfx950 with a one-wave probe).
+template <> struct Mfma<double> {
+    using acc = dx4_t;
+    static __device__ __forceinline__ acc fma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using acc = fx4_t;
+    static __device__ __forceinline__ acc fma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+__global__ void rgrid_flag_kernel(int *flag) {
+    if (threadIdx.x < 16) flag[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------ tables ----
+// E[i][k] (row-major M x N, trans = 0) or E^T[k][i] (N x M, trans = 1) of
+// exp(-2 pi i (k - N/2) y_i).  A non-finite coordinate sets *flag.
+template <typename T>
+__global__ void rgrid_table_kernel(const double *__restrict__ y, int64_t Md, int Nd, int trans,
+                                   c_t<T> *__restrict__ E, int *__restrict__ flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Md * Nd) return;
+    int64_t i, k;
+    if (trans) { k = e / Md; i = e - k * Md; }
+    else { i = e / Nd; k = e - i * Nd; }
+    const double yi = y[i];
+    if (!isfinite(yi)) {
+        atomicOr(flag, 1);
+        E[e] = cmk<T>((T)0, (T)0);
+        return;
+    }
+    const double kf = (double)(k - Nd / 2);
+    // k y - n for the integer n nearest the rounded product, in one fused
+    // operation: the exact product less n, rounded once (|r| <= 1/2 + ulp).
+    // (Written as one fma so that no contraction of the surrounding
+    // expressions can change it.)
+    const double r = fma(kf, yi, -rint(kf * yi));
+    double s, c;
+    sincospi(2.0 * r, &s, &c);
+    E[e] = cmk<T>((T)c, (T)-s);
+}
+
+// ------------------------------------------------------------- GEMM ----
+// C[b] (M x N) = A[b] (M x K) B[b] (K x N), complex, row-major with row
+// strides lda / ldb / ldc and batch strides sa / sb / sc (elements).
+struct GemmArgs {
+    const void *A;
+    const void *B;
+    void *C;
+    int64_t M, N, K;
+    int64_t lda, ldb, ldc;
+    int64_t sa, sb, sc;
+    int64_t tiles_m, tiles_n;
+};
+
+constexpr int kGB = 64;        // C tile: 64 x 64, four waves of 32 x 32
+constexpr int kGK = 16;        // contraction depth per LDS stage
+constexpr int kGThreads = 256;
+constexpr int kGPad = 1;       // LDS row padding (elements)
+
+// One workgroup per (batch, row tile, column tile).  The A tile (64 x 16) and
+// B tile (16 x 64) are staged in LDS as separate real and imaginary planes,
+// A transposed (k-major) so that the 16 lanes of an MFMA operand row read
+// consecutive words; the next K stage is loaded into registers while the
+// current one is consumed.  Wave w owns the 32 x 32 quadrant (w / 2, w % 2):
+// 2 x 2 MFMA blocks of 16 x 16, each with a real and an imaginary
+// accumulator (operand and result layouts: see Mfma).
+template <typename T>
+__global__ void __launch_bounds__(kGThreads) rgrid_gemm_kernel(GemmArgs g) {
+    using C2 = c_t<T>;
+    using Acc = typename Mfma<T>::acc;
+    __shared__ T As[2][kGK][kGB + kGPad];   // [re/im][k][row]
+    __shared__ T Bs[2][kGK][kGB + kGPad];   // [re/im][k][col]
+
+    const int64_t tiles = g.tiles_m * g.tiles_n;
+    const int64_t bidx = blockIdx.x;
+    const int64_t batch = bidx / tiles;
+    const int64_t rem = bidx - batch * tiles;
+    const int64_t tm = rem / g.tiles_n, tn = rem - tm * g.tiles_n;
+    const int64_t row0 = tm * kGB, col0 = tn * kGB;
+    const C2 *A = (const C2 *)g.A + batch * g.sa;
+    const C2 *B = (const C2 *)g.B + batch * g.sb;
+    C2 *C = (C2 *)g.C + batch * g.sc;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+
+    // register staging: 4 A and 4 B elements per thread per stage
+    C2 ra[4], rb[4];
+    auto load_stage = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + q * kGThreads;
+            const int ar = e >> 4, ak = e & 15;          // A: 64 rows x 16 k
+            const int64_t gr = row0 + ar, gk = k0 + ak;
+            ra[q] = (gr < g.M && gk < g.K) ? A[gr * g.lda + gk] : cmk<T>((T)0, (T)0);
+            const int bk = e >> 6, bc = e & 63;          // B: 16 k x 64 cols
+            const int64_t hk = k0 + bk, hc = col0 + bc;
+            rb[q] = (hk < g.K && hc < g.N) ? B[hk * g.ldb + hc] : cmk<T>((T)0, (T)0);
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + q * kGThreads;
+            const int ar = e >> 4, ak = e & 15;
+            As[0][ak][ar] = ra[q].x;
+            As[1][ak][ar] = ra[q].y;
+            const int bk = e >> 6, bc = e & 63;
+            Bs[0][bk][bc] = rb[q].x;
+            Bs[1][bk][bc] = rb[q].y;
+        }
+    };
+
+    Acc cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { cr[i][j][r] = 0; ci[i][j][r] = 0; }
+
+    load_stage(0);
+    for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
+        __syncthreads();                 // previous stage consumed
+        store_stage();
+        __syncthreads();
+        if (k0 + kGK < g.K) load_stage(k0 + kGK);
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 4) {
+            T a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a_r[i] = As[0][kk + lk][wr + i * 16 + lr];
+                a_i[i] = As[1][kk + lk][wr + i * 16 + lr];
+                a_n[i] = -a_i[i];
+                b_r[i] = Bs[0][kk + lk][wc + i * 16 + lr];
+                b_i[i] = Bs[1][kk + lk][wc + i * 16 + lr];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = Mfma<T>::fma(a_r[i], b_r[j], cr[i][j]);
+                    cr[i][j] = Mfma<T>::fma(a_n[i], b_i[j], cr[i][j]);
+                    ci[i][j] = Mfma<T>::fma(a_r[i], b_i[j], ci[i][j]);
+                    ci[i][j] = Mfma<T>::fma(a_i[i], b_r[j], ci[i][j]);
+                }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gr = row0 + wr + i * 16 + Mfma<T>::row(lk, r);
+                const int64_t gc = col0 + wc + j * 16 + lr;
+                if (gr < g.M && gc < g.N) C[gr * g.ldc + gc] = cmk<T>(cr[i][j][r], ci[i][j][r]);
+            }
+}
+
+template <typename T>
+static int launch_gemm(hipStream_t s, const void *A, const void *B, void *C, int64_t M, int64_t N, int64_t K,
+                       int64_t lda, int64_t ldb, int64_t ldc, int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
+    if (M <= 0 || N <= 0 || batch <= 0) return NFFT3_OK;
+    GemmArgs g;
+    g.A = A; g.B = B; g.C = C;
+    g.M = M; g.N = N; g.K = K;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.sa = sa; g.sb = sb; g.sc = sc;
+    g.tiles_m = (M + kGB - 1) / kGB;
+    g.tiles_n = (N + kGB - 1) / kGB;
+    const int64_t blocks = g.tiles_m * g.tiles_n * batch;
+    if (blocks > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(rgrid_gemm_kernel<T>, dim3((unsigned)blocks), dim3(kGThreads), 0, s, g);
+    NFFT3_LAUNCH_CHECK("rgrid_gemm_kernel");
+    return NFFT3_OK;
+}
+
+// ------------------------------------------------------------- host ----
+static int rgrid_tables(nfft3_rgrid_impl *g, const double *const y[3]) {
+    hipLaunchKernelGGL(rgrid_flag_kernel, dim3(1), dim3(64), 0, g->stream, g->flag);
+    NFFT3_LAUNCH_CHECK("rgrid_flag_kernel");
+    for (int d = 0; d < 3; ++d) {
+        const int64_t cnt = g->M[d] * g->N[d];
+        const unsigned blocks = (unsigned)((cnt + 255) / 256);
+        const int trans = d == 2 ? 1 : 0;
+        if (g->dtype == NFFT3_C128)
+            hipLaunchKernelGGL(rgrid_table_kernel<double>, dim3(blocks), dim3(256), 0, g->stream, y[d], g->M[d],
+                               (int)g->N[d], trans, (c_t<double> *)g->E[d], g->flag);
+        else
+            hipLaunchKernelGGL(rgrid_table_kernel<float>, dim3(blocks), dim3(256), 0, g->stream, y[d], g->M[d],
+                               (int)g->N[d], trans, (c_t<float> *)g->E[d], g->flag);
+        NFFT3_LAUNCH_CHECK("rgrid_table_kernel");
+    }
+    return NFFT3_OK;
+}
+
+int launch_rgrid_axes(nfft3_rgrid_impl *g, const double *const y[3]) { return rgrid_tables(g, y); }
+
+template <typename T>
+static int rgrid_eval_t(nfft3_rgrid_impl *g, const void *fhat, void *out) {
+    const int64_t N0 = g->N[0], N1 = g->N[1], N2 = g->N[2];
+    const int64_t M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
+    hipStream_t s = g->stream;
+    // sum over k2: (N0 N1 x N2) (N2 x M2)
+    int rc = launch_gemm<T>(s, fhat, g->E[2], g->t1, N0 * N1, M2, N2, N2, M2, M2, 1, 0, 0, 0);
+    if (rc) return rc;
+    // sum over k1, for every k0: (M1 x N1) (N1 x M2)
+    rc = launch_gemm<T>(s, g->E[1], g->t1, g->t2, M1, M2, N1, N1, M2, M2, N0, 0, N1 * M2, M1 * M2);
+    if (rc) return rc;
+    // sum over k0: (M0 x N0) (N0 x M1 M2)
+    return launch_gemm<T>(s, g->E[0], g->t2, out, M0, M1 * M2, N0, N0, M1 * M2, M1 * M2, 1, 0, 0, 0);
+}
+
+int launch_rgrid_eval(nfft3_rgrid_impl *g, const void *fhat, void *out) {
+    if (g->dtype == NFFT3_C128) return rgrid_eval_t<double>(g, fhat, out);
+    return rgrid_eval_t<float>(g, fhat, out);
+}
+
+}  // namespace nfft3
