@@ -150,6 +150,9 @@ static void free_points(nfft3_plan_impl *p) {
     (void)hipFree(p->tx); p->tx = nullptr;
     (void)hipFree(p->tperm); p->tperm = nullptr;
     (void)hipFree(p->tz); p->tz = nullptr;
+    (void)hipFree(p->chunk_base); p->chunk_base = nullptr;
+    (void)hipFree(p->sort_scratch); p->sort_scratch = nullptr;
+    p->chunk_base_cap = 0;
     p->cap_pts = 0;
 }
 
@@ -270,15 +273,16 @@ static int alloc_bins(nfft3_plan_impl *p, int T) {
     const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
     const int64_t nb = ntiles * p->n[0];
     p->bins.nbins = nb;
-    p->bins.copies = two_level_sort(p) ? 1 : kBinCopies;
-    const int64_t nc = nb * p->bins.copies;
+    const int64_t nc = nb * kBinCopies;
     // counter indices (bin copies + copy) and sorted positions are int
     if (nc + 1 > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
     NFFT3_HIP_TRY(hipMalloc(&p->bins.counts, sizeof(int) * nc));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.offsets, sizeof(int) * (nc + 1)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.scratch, sizeof(int) * (nc / 1024 + 2)));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * ntiles));
-    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (ntiles + 1)));
+    // work items are counted per (tile, segment of kItemZ z-cells)
+    const int64_t nws = ntiles * ((p->n[0] + kItemZ - 1) / kItemZ);
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_items, sizeof(int) * nws));
+    NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_item_off, sizeof(int) * (nws + 1)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_counts, sizeof(int) * ntiles));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.tile_start, sizeof(int) * (ntiles + 1)));
     NFFT3_HIP_TRY(hipMalloc(&p->bins.chunk_start, sizeof(int) * (ntiles + 1)));
@@ -389,11 +393,20 @@ int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x) {
         NFFT3_HIP_TRY(hipMalloc(&p->tz, sizeof(int) * M));
         p->cap_pts = M;
     }
-    int rc = launch_set_points(p, M, x);
-    if (rc) return rc;
-    NFFT3_HIP_TRY(hipStreamSynchronize(p->stream));
+    const int64_t bases = two_level_bases(p, M);
+    if (bases > p->chunk_base_cap) {
+        (void)hipFree(p->chunk_base);
+        (void)hipFree(p->sort_scratch);
+        p->chunk_base = nullptr;
+        p->sort_scratch = nullptr;
+        p->chunk_base_cap = 0;
+        NFFT3_HIP_TRY(hipMalloc(&p->chunk_base, sizeof(int) * (size_t)bases));
+        NFFT3_HIP_TRY(hipMalloc(&p->sort_scratch, sizeof(int) * (size_t)(bases / 1024 + 2)));
+        p->chunk_base_cap = bases;
+    }
     int flag = 0;
-    NFFT3_HIP_TRY(hipMemcpy(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost));
+    int rc = launch_set_points(p, M, x, &flag);
+    if (rc) return rc;
     if (flag & 1) return NFFT3_ERR_NONFINITE;
     p->M = M;
     p->have_points = true;

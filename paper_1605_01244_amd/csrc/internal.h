@@ -129,15 +129,14 @@ struct Bins {
     int By = 32, Bx = 32;     // tile size in cells (y, x)
     int nty = 0, ntx = 0;     // tiles per axis
     int64_t nbins = 0;        // nty * ntx * n0
-    int copies = 1;           // counters per bin: 1 (two-level sort) or kBinCopies (single-level)
-    int *counts = nullptr;    // point counts, `copies` counters per bin (device)
-    int *offsets = nullptr;   // exclusive scan of counts, nbins copies + 1 entries (device)
+    int *counts = nullptr;    // point counts, kBinCopies counters per bin (single-level sort) or one (two-level) (device)
+    int *offsets = nullptr;   // exclusive scan of counts: bin starts (device)
     int *scratch = nullptr;   // block sums of the scans
     int *tile_counts = nullptr;     // two-level sort: points (then level-2 chunks) per tile
     int *tile_start = nullptr;      // exclusive scan of the points per tile, ntiles + 1
     int *chunk_start = nullptr;     // exclusive scan of the chunks per tile, ntiles + 1
-    int *tile_items = nullptr;      // items per tile (device)
-    int *tile_item_off = nullptr;   // exclusive scan, ntiles + 1 entries (device)
+    int *tile_items = nullptr;      // items per (tile, segment of kItemZ z-cells) (device)
+    int *tile_item_off = nullptr;   // exclusive scan of tile_items, one more entry (device)
 };
 
 struct Subproblems {
@@ -176,6 +175,9 @@ struct nfft3_plan_impl {
     double *tx = nullptr;     // two-level sort: folded points in tile order (scratch, (M,3))
     int *tperm = nullptr;     // two-level sort: caller index in tile order (scratch)
     int *tz = nullptr;        // two-level sort: z-cell in tile order (scratch)
+    int *chunk_base = nullptr;      // two-level sort: runs per (chunk, key) (scratch)
+    int *sort_scratch = nullptr;    // two-level sort: block sums of the run scan
+    int64_t chunk_base_cap = 0;
     int *flag = nullptr;      // device status word (non-finite points)
     Bins bins;
     int tile_req = kMaxTile;  // requested tile edge (By, Bx may be smaller)
@@ -233,9 +235,11 @@ bool factor_radices(int n, std::vector<int> &rad);
 int launch_grid_forward(nfft3_plan_impl *p, const void *fhat, void *grid, int deriv_axis);
 int launch_grid_adjoint(nfft3_plan_impl *p, void *grid, void *fhat);
 // points (points.hip)
-int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x);
-// whether set_points uses the two-level (LDS) sort for the plan's tiling
-bool two_level_sort(const nfft3_plan_impl *p);
+// sorts the points and cuts the work items; *flag = the device status word
+// (bit 0: a non-finite coordinate).  Synchronises the plan's stream once.
+int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x, int *flag);
+// chunk bases the two-level sort needs for M points, -1 if it is not used
+int64_t two_level_bases(const nfft3_plan_impl *p, int64_t M);
 // *equal = 1 when the sorted points are those of x (no new sort needed)
 int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equal);
 // window sums and their point derivative (interp.hip)

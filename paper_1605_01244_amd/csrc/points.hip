@@ -7,6 +7,8 @@
 // work items of at most maxpts points spanning at most kItemZ z-cells; a
 // workgroup of the window-sum kernels takes one item and streams the z-planes
 // of its tile (plus the stencil halo) through LDS.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nfft3 {
@@ -152,82 +154,167 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
 // ---- two-level counting sort (tile, then z within the tile) ---------------
 // One global atomic per point (the single-level sort above) runs at the
 // device's atomic rate, and its scatter writes 24 bytes at a random place
-// per point.  The two-level sort counts in LDS instead: a workgroup takes a
-// chunk of kSortChunk points, ranks them within the chunk with LDS atomics
-// per key, then reserves each key's run with one global atomic per (chunk,
-// key) present; a point's rank in its key is the run's base plus its local
-// rank.  Level 1 keys by tile and scatters the folded points into tile order;
-// level 2 walks each tile's points in chunks that never cross a tile, keys
-// them by z-cell and scatters them into (tile, z) order.  Every run of a
-// chunk and key is contiguous, so the scatters write in runs.  The order
-// within a (tile, z) bin depends on the atomics (as before).
-constexpr int kSortChunk = 4096;                 // points per workgroup
+// per point.  The two-level sort works on chunks of kSortChunk points per
+// workgroup.  Level 1 keys by tile (input order -> tile order): a count pass
+// writes each chunk's per-tile counts into a (tile, chunk) matrix, whose
+// exclusive scan gives every (tile, chunk) run its final start (no
+// atomics: one counter per tile would take an atomic from every chunk).
+// Level 2 keys by z-cell within chunks that never cross a tile (tile order
+// -> (tile, z) order); its bins are many and lightly contended, so a run is
+// reserved with one global atomic per (chunk, bin).  A scatter pass ranks
+// the chunk again in LDS (any order within a key will do: the run's length
+// is what was counted), computes each point's destination, and then moves
+// the data one field at a time through LDS: coalesced reads in the chunk's
+// order, coalesced runs of writes in the sorted order.  The order within a
+// (tile, z) bin depends on the atomics (as before).
+constexpr int kSortChunk = 2048;                 // points per workgroup
 constexpr int kSortPer = kSortChunk / kPtThreads;
-constexpr int kSortMaxTiles = 8192;              // LDS: two ints per tile
+constexpr int kSortMaxTiles = 8192;              // LDS counters of level 1
+// (tile, chunk) counts of level 1 and (chunk, z) bases of level 2: at most
+constexpr int64_t kSortMaxBases = int64_t(1) << 25;
 
-// level 1: local ranks by tile, a global base per (chunk, tile) present
+__device__ __forceinline__ int point_tile(const double *xp, const BinGeom &g, bool &finite) {
+    finite = isfinite(xp[0]) && isfinite(xp[1]) && isfinite(xp[2]);
+    if (!finite) return 0;         // reported through the flag; the sort is then discarded
+    const int c1 = cell_of(fold_unit(xp[1]), g.n1, g.in1);
+    const int c2 = cell_of(fold_unit(xp[2]), g.n2, g.in2);
+    return (c1 / g.By) * g.ntx + c2 / g.Bx;
+}
+
+// In-place exclusive scan of n LDS ints by the workgroup (kPtThreads
+// threads, contiguous segments per thread); sh holds kPtThreads ints.
+__device__ void lds_exclusive_scan(int *a, int n, int *sh) {
+    const int per = (n + kPtThreads - 1) / kPtThreads;
+    const int b = threadIdx.x * per, e = min(n, b + per);
+    int sum = 0;
+    for (int i = b; i < e; ++i) sum += a[i];
+    int total;
+    int run = block_exclusive_scan(sum, sh, total);
+    for (int i = b; i < e; ++i) {
+        const int v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+}
+
+// Move one field of a chunk into sorted order through LDS: value v[i] of
+// the thread's i-th point goes to slot sl[i]; slot s (s = threadIdx + k 256)
+// is written to out[dest[k]] (stride elements apart for interleaved output).
+template <typename V>
+__device__ __forceinline__ void stage_field(V *buf, const V *v, const int *sl, const int64_t *dest, int nv, V *out,
+                                            int stride, int comp) {
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i)
+        if (i * kPtThreads + (int)threadIdx.x < nv) buf[sl[i]] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) {
+        const int s = k * kPtThreads + threadIdx.x;
+        if (s < nv) out[dest[k] * stride + comp] = buf[s];
+    }
+    __syncthreads();
+}
+
+// level 1 count: counts[t * nchunks + chunk]
 __global__ void __launch_bounds__(kPtThreads)
-tile_rank_kernel(const double *__restrict__ x, int64_t M, BinGeom g, int ntiles, int *__restrict__ tile_counts,
-                 int *__restrict__ trank, int *__restrict__ flag) {
-    extern __shared__ int sh[];                  // [0, ntiles): counts, then bases
-    int *cnt = sh, *base = sh + ntiles;
+tile_count_kernel(const double *__restrict__ x, int64_t M, BinGeom g, int ntiles, int *__restrict__ counts,
+                  int *__restrict__ flag) {
+    extern __shared__ int cnt[];                 // ntiles
     for (int t = threadIdx.x; t < ntiles; t += kPtThreads) cnt[t] = 0;
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
-    int key[kSortPer], lr[kSortPer];
-#pragma unroll
+    bool bad = false;
+#pragma unroll 4
     for (int i = 0; i < kSortPer; ++i) {
         const int64_t j = c0 + i * kPtThreads + threadIdx.x;
-        key[i] = -1;
         if (j < M) {
-            const double *xp = x + 3 * j;
-            int t = 0;
-            if (isfinite(xp[0]) && isfinite(xp[1]) && isfinite(xp[2])) {
-                const int c1 = cell_of(fold_unit(xp[1]), g.n1, g.in1);
-                const int c2 = cell_of(fold_unit(xp[2]), g.n2, g.in2);
-                t = (c1 / g.By) * g.ntx + c2 / g.Bx;
-            } else {
-                atomicOr(flag, 1);
+            bool finite;
+            const int t = point_tile(x + 3 * j, g, finite);
+            bad = bad || !finite;
+            atomicAdd(&cnt[t], 1);
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += kPtThreads) counts[(int64_t)t * gridDim.x + blockIdx.x] = cnt[t];
+}
+
+// tile starts from the scanned (tile, chunk) matrix: tile_start[t] = run
+// start of (t, chunk 0); tile_start[ntiles] = M
+__global__ void tile_start_kernel(const int *__restrict__ starts, int nchunks, int ntiles, int M,
+                                  int *__restrict__ tile_start) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles) tile_start[t] = starts[(int64_t)t * nchunks];
+    if (t == ntiles) tile_start[t] = M;
+}
+
+// level 1 scatter: folded coordinates (three arrays), caller index and
+// z-cell in tile order; each point is read once and held in registers
+__global__ void __launch_bounds__(kPtThreads)
+tile_scatter_kernel(const double *__restrict__ x, int64_t M, BinGeom g, int ntiles, const int *__restrict__ starts,
+                    double *__restrict__ tx, int *__restrict__ tperm, int *__restrict__ tz) {
+    extern __shared__ __align__(16) int sm[];    // ntiles offsets (8-byte aligned), then a field of the chunk
+    __shared__ int sh[kPtThreads];
+    int *lofs = sm;
+    double *buf = (double *)(sm + ((ntiles + 1) & ~1));
+    for (int t = threadIdx.x; t < ntiles; t += kPtThreads) lofs[t] = 0;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+    const int nv = (int)min<int64_t>(kSortChunk, M - c0);
+    int key[kSortPer], sl[kSortPer], zc[kSortPer];
+    double f[3][kSortPer];
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i) {
+        const int li = i * kPtThreads + threadIdx.x;
+        key[i] = 0;
+        sl[i] = 0;
+        zc[i] = 0;
+        f[0][i] = f[1][i] = f[2][i] = 0.0;
+        if (li < nv) {
+            const double *xp = x + 3 * (c0 + li);
+            const double a = xp[0], b = xp[1], c = xp[2];
+            // a non-finite point goes to tile 0 at the origin (reported
+            // through the flag by tile_count_kernel)
+            if (isfinite(a) && isfinite(b) && isfinite(c)) {
+                f[0][i] = fold_unit(a);
+                f[1][i] = fold_unit(b);
+                f[2][i] = fold_unit(c);
             }
-            key[i] = t;
-            lr[i] = atomicAdd(&cnt[t], 1);
+            const int c1 = cell_of(f[1][i], g.n1, g.in1), c2 = cell_of(f[2][i], g.n2, g.in2);
+            key[i] = (c1 / g.By) * g.ntx + c2 / g.Bx;
+            zc[i] = cell_of(f[0][i], g.n0, g.in0);
+            sl[i] = atomicAdd(&lofs[key[i]], 1);
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < ntiles; t += kPtThreads)
-        if (cnt[t]) base[t] = atomicAdd(&tile_counts[t], cnt[t]);
-    __syncthreads();
+    lds_exclusive_scan(lofs, ntiles, sh);
+    // destination of each slot: the (tile, chunk) run start + rank in the run
+    int *dslot = (int *)buf;
 #pragma unroll
     for (int i = 0; i < kSortPer; ++i) {
-        const int64_t j = c0 + i * kPtThreads + threadIdx.x;
-        if (key[i] >= 0) trank[j] = base[key[i]] + lr[i];
+        const int li = i * kPtThreads + threadIdx.x;
+        if (li < nv) {
+            const int r = sl[i];
+            sl[i] = lofs[key[i]] + r;
+            dslot[sl[i]] = starts[(int64_t)key[i] * gridDim.x + blockIdx.x] + r;
+        }
     }
-}
-
-// level 1 scatter: folded coordinates, caller index and z-cell in tile order
-__global__ void __launch_bounds__(kPtThreads)
-tile_scatter_kernel(const double *__restrict__ x, int64_t M, BinGeom g, const int *__restrict__ tile_start,
-                    const int *__restrict__ trank, double *__restrict__ tx, int *__restrict__ tperm,
-                    int *__restrict__ tz) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
-    const double *xp = x + 3 * j;
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    // a non-finite point (reported through the flag; the sort's result is
-    // then discarded) goes to tile 0 at the origin, as tile_rank_kernel put it
-    if (isfinite(xp[0]) && isfinite(xp[1]) && isfinite(xp[2])) {
-        f0 = fold_unit(xp[0]);
-        f1 = fold_unit(xp[1]);
-        f2 = fold_unit(xp[2]);
+    __syncthreads();
+    int64_t dest[kSortPer];
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) {
+        const int s = k * kPtThreads + threadIdx.x;
+        dest[k] = s < nv ? dslot[s] : 0;
     }
-    const int c1 = cell_of(f1, g.n1, g.in1), c2 = cell_of(f2, g.n2, g.in2);
-    const int t = (c1 / g.By) * g.ntx + c2 / g.Bx;
-    const int64_t pos = (int64_t)tile_start[t] + trank[j];
-    tx[3 * pos + 0] = f0;
-    tx[3 * pos + 1] = f1;
-    tx[3 * pos + 2] = f2;
-    tperm[pos] = (int)j;
-    tz[pos] = cell_of(f0, g.n0, g.in0);
+    __syncthreads();
+    for (int d = 0; d < 3; ++d) stage_field<double>(buf, f[d], sl, dest, nv, tx + d * M, 1, 0);
+    int *ibuf = (int *)buf;
+    int v[kSortPer];
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i) v[i] = (int)(c0 + i * kPtThreads + threadIdx.x);
+    stage_field<int>(ibuf, v, sl, dest, nv, tperm, 1, 0);
+    stage_field<int>(ibuf, zc, sl, dest, nv, tz, 1, 0);
 }
 
 // chunks of level 2 per tile: ceil(count / kSortChunk)
@@ -252,54 +339,101 @@ __device__ __forceinline__ bool level2_chunk(const int *__restrict__ chunk_start
     return true;
 }
 
-// level 2: local ranks by z-cell within a tile's chunk, a global base per
-// (chunk, bin) present
+// level 2 count: chunk bases per (chunk, z) present
 __global__ void __launch_bounds__(kPtThreads)
-z_rank_kernel(const int *__restrict__ tz, const int *__restrict__ tile_start, const int *__restrict__ chunk_start,
-              int ntiles, int n0, int *__restrict__ bin_counts, int *__restrict__ zrank) {
-    extern __shared__ int sh[];                  // [0, n0): counts, then bases
-    int *cnt = sh, *base = sh + n0;
+z_count_kernel(const int *__restrict__ tz, const int *__restrict__ tile_start, const int *__restrict__ chunk_start,
+               int ntiles, int n0, int *__restrict__ bin_counts, int *__restrict__ chunk_base) {
+    extern __shared__ int cnt[];                 // n0
     int t, lo, hi;
     if (!level2_chunk(chunk_start, tile_start, ntiles, blockIdx.x, t, lo, hi)) return;
     for (int z = threadIdx.x; z < n0; z += kPtThreads) cnt[z] = 0;
     __syncthreads();
-    int key[kSortPer], lr[kSortPer];
-#pragma unroll
-    for (int i = 0; i < kSortPer; ++i) {
-        const int64_t p = (int64_t)lo + i * kPtThreads + threadIdx.x;
-        key[i] = -1;
-        if (p < hi) {
-            key[i] = tz[p];
-            lr[i] = atomicAdd(&cnt[key[i]], 1);
-        }
-    }
+    for (int64_t p = (int64_t)lo + threadIdx.x; p < hi; p += kPtThreads) atomicAdd(&cnt[tz[p]], 1);
     __syncthreads();
     int *bc = bin_counts + (int64_t)t * n0;
+    int *cb = chunk_base + (int64_t)blockIdx.x * n0;
     for (int z = threadIdx.x; z < n0; z += kPtThreads)
-        if (cnt[z]) base[z] = atomicAdd(&bc[z], cnt[z]);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kSortPer; ++i) {
-        const int64_t p = (int64_t)lo + i * kPtThreads + threadIdx.x;
-        if (key[i] >= 0) zrank[p] = base[key[i]] + lr[i];
-    }
+        if (cnt[z]) cb[z] = atomicAdd(&bc[z], cnt[z]);
 }
 
 // level 2 scatter into (tile, z) order
 __global__ void __launch_bounds__(kPtThreads)
 z_scatter_kernel(const double *__restrict__ tx, const int *__restrict__ tperm, const int *__restrict__ tz,
-                 const int *__restrict__ zrank, int64_t M, BinGeom g, const int *__restrict__ bin_start,
+                 int64_t M, const int *__restrict__ tile_start, const int *__restrict__ chunk_start, int ntiles,
+                 int n0, const int *__restrict__ bin_start, const int *__restrict__ chunk_base,
                  double *__restrict__ xs, int *__restrict__ perm) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
-    const double f0 = tx[3 * p + 0], f1 = tx[3 * p + 1], f2 = tx[3 * p + 2];
-    const int c1 = cell_of(f1, g.n1, g.in1), c2 = cell_of(f2, g.n2, g.in2);
-    const int t = (c1 / g.By) * g.ntx + c2 / g.Bx;
-    const int64_t pos = (int64_t)bin_start[(int64_t)t * g.in0 + tz[p]] + zrank[p];
-    xs[3 * pos + 0] = f0;
-    xs[3 * pos + 1] = f1;
-    xs[3 * pos + 2] = f2;
-    perm[pos] = tperm[p];
+    extern __shared__ __align__(16) int sm[];    // n0 offsets (8-byte aligned), then three fields of the chunk
+    __shared__ int sh[kPtThreads];
+    int t, lo, hi;
+    if (!level2_chunk(chunk_start, tile_start, ntiles, blockIdx.x, t, lo, hi)) return;
+    int *lofs = sm;
+    double *buf = (double *)(sm + ((n0 + 1) & ~1));
+    for (int z = threadIdx.x; z < n0; z += kPtThreads) lofs[z] = 0;
+    __syncthreads();
+    const int nv = hi - lo;
+    int key[kSortPer], sl[kSortPer];
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i) {
+        const int li = i * kPtThreads + threadIdx.x;
+        key[i] = 0;
+        sl[i] = 0;
+        if (li < nv) {
+            key[i] = tz[(int64_t)lo + li];
+            sl[i] = atomicAdd(&lofs[key[i]], 1);
+        }
+    }
+    __syncthreads();
+    lds_exclusive_scan(lofs, n0, sh);
+    const int *cb = chunk_base + (int64_t)blockIdx.x * n0;
+    const int *bs = bin_start + (int64_t)t * n0;
+    int *dslot = (int *)buf;
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i) {
+        const int li = i * kPtThreads + threadIdx.x;
+        if (li < nv) {
+            const int r = sl[i];
+            sl[i] = lofs[key[i]] + r;
+            dslot[sl[i]] = bs[key[i]] + cb[key[i]] + r;
+        }
+    }
+    __syncthreads();
+    int64_t dest[kSortPer];
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) {
+        const int s = k * kPtThreads + threadIdx.x;
+        dest[k] = s < nv ? dslot[s] : 0;
+    }
+    __syncthreads();
+    // the three coordinates go through LDS together, so each point's 24
+    // bytes are written at once (three strided passes would leave partly
+    // written lines between passes)
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i) {
+        const int li = i * kPtThreads + threadIdx.x;
+        if (li < nv) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) buf[d * kSortChunk + sl[i]] = tx[d * M + lo + li];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortPer; ++k) {
+        const int s = k * kPtThreads + threadIdx.x;
+        if (s < nv) {
+            double *o = xs + 3 * dest[k];
+            o[0] = buf[s];
+            o[1] = buf[kSortChunk + s];
+            o[2] = buf[2 * kSortChunk + s];
+        }
+    }
+    __syncthreads();
+    int v[kSortPer];
+#pragma unroll
+    for (int i = 0; i < kSortPer; ++i) {
+        const int li = i * kPtThreads + threadIdx.x;
+        v[i] = li < nv ? tperm[(int64_t)lo + li] : 0;
+    }
+    stage_field<int>((int *)buf, v, sl, dest, nv, perm, 1, 0);
 }
 
 // ---- do the sorted points still describe x? ------------------------------
@@ -340,68 +474,75 @@ int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equ
     return NFFT3_OK;
 }
 
-// ---- work items: walk each tile column's z-cells (one wave per tile) ------
-// A new item starts when adding the next cell would exceed maxpts points or
-// the item would span more than kItemZ z-cells; a cell holding more than
-// maxpts points becomes ceil(count/maxpts) items of its own.  WRITE=false
-// counts the items of each tile, WRITE=true emits (tile, p_lo, p_hi, 0).
-// The wave stages the tile's n0 + 1 bin starts in LDS with coalesced loads
-// (when they fit), then one lane walks them: the walk is sequential, so
-// reading its inputs from HBM one dependent load at a time dominated.
-constexpr int kItemWaves = 4;            // tiles per workgroup
+// ---- work items: greedy walks over segments of each tile column ----------
+// A tile column is cut into segments of kItemZ z-cells, one per thread;
+// within its segment a thread walks the cells: a new item starts when adding
+// the next cell would exceed maxpts points, and a cell holding more than
+// maxpts points becomes ceil(count/maxpts) items of its own.  Items never
+// cross a segment boundary, so none spans more than kItemZ cells.
+// WRITE=false counts the items of each (tile, segment), WRITE=true emits
+// (tile, p_lo, p_hi, 0) at the scanned offsets, i.e. in (tile, z) order.
+// (One walk per tile column made each step wait on the previous one; the
+// segments run side by side.)
+constexpr int kItemThreads = 64;         // one wave per workgroup: the walks spread over more CUs
 
 template <bool WRITE>
-__global__ void __launch_bounds__(64 * kItemWaves)
-items_kernel(const int *__restrict__ offsets, int copies, int ntiles, int n0, int maxpts,
+__global__ void __launch_bounds__(kItemThreads)
+items_kernel(const int *__restrict__ offsets, int copies, int ntiles, int n0, int nseg, int maxpts,
              int *__restrict__ item_count, const int *__restrict__ item_offset, int4 *__restrict__ items,
-             int use_lds) {
-    extern __shared__ int sofs[];        // kItemWaves x (n0 + 1) bin starts
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * kItemWaves + wave;
-    const bool valid = tile < ntiles;
+             int64_t cap, int *__restrict__ flag) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)ntiles * nseg) return;
+    const int tile = (int)(q / nseg), seg = (int)(q - (int64_t)tile * nseg);
+    const int z0 = seg * kItemZ, z1 = min(n0, z0 + kItemZ);
     // bin (tile, z) spans offsets[(tile n0 + z) K] .. offsets[(tile n0 + z + 1) K],
     // K = copies counters per bin
-    const int *g = offsets + (int64_t)(valid ? tile : 0) * n0 * copies;
-    const int *ofs = g;
-    int stride = copies;
-    if (use_lds) {
-        int *sw = sofs + wave * (n0 + 1);
-        if (valid)
-            for (int z = lane; z <= n0; z += 64) sw[z] = g[(int64_t)z * copies];
-        __syncthreads();
-        ofs = sw;
-        stride = 1;
-    }
-    if (!valid || lane != 0) return;
+    const int *g = offsets + (int64_t)tile * n0 * copies;
     int k = 0;
-    int64_t w = WRITE ? item_offset[tile] : 0;
-    int cur = 0, z_start = 0, p_start = 0;
-    int onext = ofs[0];
-    for (int z = 0; z < n0; ++z) {
-        const int oz = onext;
-        onext = ofs[(z + 1) * stride];
-        const int c = onext - oz;
-        if (c == 0) continue;
-        if (cur > 0 && (cur + c > maxpts || z - z_start >= kItemZ)) {
-            if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
+    const int64_t w = WRITE ? item_offset[q] : 0;
+    int cur = 0, p_start = 0;
+    // the segment's kItemZ + 1 bin starts, all loads in flight together
+    int o[kItemZ + 1];
+#pragma unroll
+    for (int e = 0; e <= kItemZ; ++e) o[e] = g[(int64_t)min(z0 + e, z1) * copies];
+#pragma unroll
+    for (int e = 0; e < kItemZ; ++e) {
+        const int z = z0 + e;
+        const int oz = o[e];
+        const int c = o[e + 1] - oz;
+        if (z >= z1 || c == 0) continue;
+        if (cur > 0 && cur + c > maxpts) {
+            if (WRITE && w + k < cap) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
             ++k;
             cur = 0;
         }
         if (c > maxpts) {     // a dense cell on its own
-            for (int s = 0; s < c; s += maxpts) {
-                if (WRITE) items[w + k] = make_int4(tile, oz + s, oz + min(c, s + maxpts), 0);
+            for (int s0 = 0; s0 < c; s0 += maxpts) {
+                if (WRITE && w + k < cap) items[w + k] = make_int4(tile, oz + s0, oz + min(c, s0 + maxpts), 0);
                 ++k;
             }
             continue;
         }
-        if (cur == 0) { z_start = z; p_start = oz; }
+        if (cur == 0) p_start = oz;
         cur += c;
     }
     if (cur > 0) {
-        if (WRITE) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
+        if (WRITE && w + k < cap) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
         ++k;
     }
-    if (!WRITE) item_count[tile] = k;
+    if (!WRITE) item_count[q] = k;
+    // the list is sized by max_items; should it ever be short, report it
+    if (WRITE && w + k > cap) atomicOr(flag, 4);
+}
+
+// Items of a tiling with ntiles tile columns of n0 cells for M points, at
+// most: an item cut because the next (regular) cell would overflow it holds,
+// with its successor in the segment, more than maxpts points, so such items
+// number below 2 P / maxpts for the P points of regular cells; a dense cell
+// of c points makes under 2 c / maxpts items and cuts at most one; each of
+// the ceil(n0 / kItemZ) segments of a column ends one more.
+int64_t max_items(int64_t M, int64_t ntiles, int64_t n0, int maxpts) {
+    return 3 * ((M + maxpts - 1) / maxpts) + ntiles * (n0 / kItemZ + 2) + 1;
 }
 
 // Single-level sort (one global atomic per point, kBinCopies counters per
@@ -428,60 +569,76 @@ static int sort_single_level(nfft3_plan_impl *p, int64_t M, const double *x, con
     return NFFT3_OK;
 }
 
-// Two-level sort (see tile_rank_kernel); bins.offsets receives the nbins + 1
+// Two-level sort (see tile_count_kernel); bins.offsets receives the nbins + 1
 // bin starts.
 static int sort_two_level(nfft3_plan_impl *p, int64_t M, const double *x, const BinGeom &g) {
     const int ntiles = g.nty * g.ntx;
     const int64_t nb = p->bins.nbins;
     hipStream_t s = p->stream;
     Bins &B = p->bins;
-    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, B.tile_counts,
-                       (int64_t)ntiles, 0);
-    NFFT3_LAUNCH_CHECK("fill_int_kernel");
+    const int chunks1 = (int)((M + kSortChunk - 1) / kSortChunk);
     hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, B.counts, nb, 0);
     NFFT3_LAUNCH_CHECK("fill_int_kernel");
-    const unsigned chunks1 = (unsigned)((M + kSortChunk - 1) / kSortChunk);
-    allow_lds((const void *)tile_rank_kernel, sizeof(int) * 2 * ntiles);
+    const size_t lds1 = sizeof(int) * (((size_t)ntiles + 1) & ~(size_t)1) + sizeof(double) * kSortChunk;
+    const size_t lds2 = sizeof(int) * (((size_t)g.in0 + 1) & ~(size_t)1) + 3 * sizeof(double) * kSortChunk;
+    allow_lds((const void *)tile_count_kernel, sizeof(int) * ntiles);
+    allow_lds((const void *)tile_scatter_kernel, lds1);
+    allow_lds((const void *)z_scatter_kernel, lds2);
     if (M > 0) {
-        hipLaunchKernelGGL(tile_rank_kernel, dim3(chunks1), dim3(kPtThreads), sizeof(int) * 2 * ntiles, s, x, M, g,
-                           ntiles, B.tile_counts, p->bin_of, p->flag);
-        NFFT3_LAUNCH_CHECK("tile_rank_kernel");
-    }
-    int rc = exclusive_scan(s, B.tile_counts, B.tile_start, B.scratch, ntiles);
-    if (rc) return rc;
-    const unsigned blocks = (unsigned)((M + kPtThreads - 1) / kPtThreads);
-    if (M > 0) {
-        hipLaunchKernelGGL(tile_scatter_kernel, dim3(blocks), dim3(kPtThreads), 0, s, x, M, g, B.tile_start,
-                           p->bin_of, p->tx, p->tperm, p->tz);
+        // (tile, chunk) counts -> run starts in place
+        hipLaunchKernelGGL(tile_count_kernel, dim3(chunks1), dim3(kPtThreads), sizeof(int) * ntiles, s, x, M, g,
+                           ntiles, p->chunk_base, p->flag);
+        NFFT3_LAUNCH_CHECK("tile_count_kernel");
+        int rc = exclusive_scan(s, p->chunk_base, p->chunk_base, p->sort_scratch, (int64_t)chunks1 * ntiles);
+        if (rc) return rc;
+        hipLaunchKernelGGL(tile_start_kernel, dim3((unsigned)((ntiles + 256) / 256)), dim3(256), 0, s, p->chunk_base,
+                           chunks1, ntiles, (int)M, B.tile_start);
+        NFFT3_LAUNCH_CHECK("tile_start_kernel");
+        hipLaunchKernelGGL(tile_scatter_kernel, dim3(chunks1), dim3(kPtThreads), lds1, s, x, M, g, ntiles,
+                           p->chunk_base, p->tx, p->tperm, p->tz);
         NFFT3_LAUNCH_CHECK("tile_scatter_kernel");
+    } else {
+        hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((ntiles + 256) / 256)), dim3(256), 0, s, B.tile_start,
+                           (int64_t)ntiles + 1, 0);
+        NFFT3_LAUNCH_CHECK("fill_int_kernel");
     }
     hipLaunchKernelGGL(tile_chunks_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, B.tile_start,
                        ntiles, B.tile_counts);
     NFFT3_LAUNCH_CHECK("tile_chunks_kernel");
-    rc = exclusive_scan(s, B.tile_counts, B.chunk_start, B.scratch, ntiles);
+    int rc = exclusive_scan(s, B.tile_counts, B.chunk_start, B.scratch, ntiles);
     if (rc) return rc;
     // level-2 chunks: at most one partial chunk per tile beyond M / kSortChunk
+    // (blocks past the last chunk return at once)
     const int64_t chunks2 = (M + kSortChunk - 1) / kSortChunk + ntiles;
     if (M > 0) {
-        hipLaunchKernelGGL(z_rank_kernel, dim3((unsigned)chunks2), dim3(kPtThreads), sizeof(int) * 2 * g.in0, s, p->tz,
-                           B.tile_start, B.chunk_start, ntiles, g.in0, B.counts, p->rank);
-        NFFT3_LAUNCH_CHECK("z_rank_kernel");
+        hipLaunchKernelGGL(z_count_kernel, dim3((unsigned)chunks2), dim3(kPtThreads), sizeof(int) * g.in0, s, p->tz,
+                           B.tile_start, B.chunk_start, ntiles, g.in0, B.counts, p->chunk_base);
+        NFFT3_LAUNCH_CHECK("z_count_kernel");
     }
     rc = exclusive_scan(s, B.counts, B.offsets, B.scratch, nb);
     if (rc) return rc;
     if (M > 0) {
-        hipLaunchKernelGGL(z_scatter_kernel, dim3(blocks), dim3(kPtThreads), 0, s, p->tx, p->tperm, p->tz, p->rank, M,
-                           g, B.offsets, p->xs, p->perm);
+        hipLaunchKernelGGL(z_scatter_kernel, dim3((unsigned)chunks2), dim3(kPtThreads), lds2, s, p->tx, p->tperm,
+                           p->tz, M, B.tile_start, B.chunk_start, ntiles, g.in0, B.offsets, p->chunk_base, p->xs,
+                           p->perm);
         NFFT3_LAUNCH_CHECK("z_scatter_kernel");
     }
     return NFFT3_OK;
 }
 
-bool two_level_sort(const nfft3_plan_impl *p) {
-    return (int64_t)p->bins.nty * p->bins.ntx <= kSortMaxTiles;
+// Entries of the two-level sort's run buffer for M points (level 1: the
+// (tile, chunk) matrix and its scan; then level 2: the (chunk, z) bases), or
+// -1 when the plan's tiling or M calls for the single-level sort.
+int64_t two_level_bases(const nfft3_plan_impl *p, int64_t M) {
+    const int64_t ntiles = (int64_t)p->bins.nty * p->bins.ntx;
+    if (ntiles > kSortMaxTiles) return -1;
+    const int64_t c1 = (M + kSortChunk - 1) / kSortChunk;
+    // level-1 (tile, chunk) matrix and its scan total, then level-2 (chunk, z) bases
+    const int64_t need = std::max(c1 * ntiles + 1, (c1 + ntiles) * p->n[0]);
+    return need <= kSortMaxBases ? need : -1;
 }
 
-int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
+int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x, int *flag_out) {
     BinGeom g;
     g.n0 = (double)p->n[0]; g.n1 = (double)p->n[1]; g.n2 = (double)p->n[2];
     g.in0 = (int)p->n[0]; g.in1 = (int)p->n[1]; g.in2 = (int)p->n[2];
@@ -491,38 +648,41 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x) {
     hipStream_t s = p->stream;
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, s, p->flag, (int64_t)16, 0);
     NFFT3_LAUNCH_CHECK("fill_int_kernel");
-    const bool two = two_level_sort(p);
+    const bool two = two_level_bases(p, M) >= 0;
     int rc = two ? sort_two_level(p, M, x, g) : sort_single_level(p, M, x, g);
     if (rc) return rc;
     const int copies = two ? 1 : kBinCopies;
-    // work items
-    const unsigned tb = (unsigned)((ntiles + kItemWaves - 1) / kItemWaves);
-    const size_t ilds = sizeof(int) * kItemWaves * ((size_t)g.in0 + 1);
-    const int use_lds = ilds <= 64 * 1024 ? 1 : 0;
-    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(64 * kItemWaves), use_lds ? ilds : 0, s, p->bins.offsets,
-                       copies, ntiles, g.in0, p->sub.maxpts, p->bins.tile_items, (const int *)nullptr,
-                       (int4 *)nullptr, use_lds);
-    NFFT3_LAUNCH_CHECK("items_kernel");
-    rc = exclusive_scan(s, p->bins.tile_items, p->bins.tile_item_off, p->bins.scratch, ntiles);
-    if (rc) return rc;
-    // the item count is needed on the host to size the item list and the launches
-    int nitems = 0;
-    NFFT3_HIP_TRY(hipMemcpyAsync(&nitems, p->bins.tile_item_off + ntiles, sizeof(int), hipMemcpyDeviceToHost, s));
-    NFFT3_HIP_TRY(hipStreamSynchronize(s));
-    if (nitems > p->sub.cap) {
+    // work items: counted, scanned and written on the device into a list
+    // sized for the most items M points can make
+    const int64_t cap = max_items(M, ntiles, g.in0, p->sub.maxpts);
+    if (cap > p->sub.cap) {
         (void)hipFree(p->sub.items);
         p->sub.items = nullptr;
         p->sub.cap = 0;
-        NFFT3_HIP_TRY(hipMalloc(&p->sub.items, sizeof(int4) * (size_t)std::max(nitems, 1)));
-        p->sub.cap = nitems;
+        NFFT3_HIP_TRY(hipMalloc(&p->sub.items, sizeof(int4) * (size_t)cap));
+        p->sub.cap = cap;
     }
+    const int nseg = (int)((g.in0 + kItemZ - 1) / kItemZ);
+    const int64_t nws = (int64_t)ntiles * nseg;
+    const unsigned tb = (unsigned)((nws + kItemThreads - 1) / kItemThreads);
+    hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(kItemThreads), 0, s, p->bins.offsets, copies, ntiles, g.in0, nseg,
+                       p->sub.maxpts, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr, (int64_t)0, p->flag);
+    NFFT3_LAUNCH_CHECK("items_kernel");
+    rc = exclusive_scan(s, p->bins.tile_items, p->bins.tile_item_off, p->bins.scratch, nws);
+    if (rc) return rc;
+    hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(kItemThreads), 0, s, p->bins.offsets, copies, ntiles, g.in0, nseg,
+                       p->sub.maxpts, (int *)nullptr, (const int *)p->bins.tile_item_off, p->sub.items, p->sub.cap,
+                       p->flag);
+    NFFT3_LAUNCH_CHECK("items_kernel");
+    // the item count sizes the window-sum launches; the flag reports
+    // non-finite points: one synchronisation for both
+    int nitems = 0, flag = 0;
+    NFFT3_HIP_TRY(hipMemcpyAsync(&nitems, p->bins.tile_item_off + nws, sizeof(int), hipMemcpyDeviceToHost, s));
+    NFFT3_HIP_TRY(hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    NFFT3_HIP_TRY(hipStreamSynchronize(s));
+    if (flag & 4) return NFFT3_ERR_INVALID_ARG;    // item list too short (never expected)
     p->sub.count = nitems;
-    if (nitems > 0) {
-        hipLaunchKernelGGL((items_kernel<true>), dim3(tb), dim3(64 * kItemWaves), use_lds ? ilds : 0, s,
-                           p->bins.offsets, copies, ntiles, g.in0, p->sub.maxpts, (int *)nullptr,
-                           (const int *)p->bins.tile_item_off, p->sub.items, use_lds);
-        NFFT3_LAUNCH_CHECK("items_kernel");
-    }
+    *flag_out = flag;
     return NFFT3_OK;
 }
 

@@ -24,7 +24,9 @@ namespace nfft3 {
 // rint(p - 4 q1), |.| <= 2, in its low word; and rint(p) = 4 q1 +
 // rint(p - 4 q1), with one rounding of the exact product.  The error is at
 // most 2^(e-54), half an FP64 ulp of the chunk's largest value (2^-53 max|f|
-// up to the 1.0001 margin on the scale).  Each plane is flushed once per
+// up to the 1.0001 margin on the scale).  The largest value is taken in f's
+// own precision, so any finite range works (1e-300 and 1e300 alike); NaN and
+// infinite values are kept out of the sums and turn the result into NaN.  Each plane is flushed once per
 // chunk: converted back (exact power-of-two scaling) and added to the grid
 // with global atomics, whose rate bounds the kernel when a 512-point item is
 // taken in two chunks, hence two points per thread (one walk and one flush
@@ -43,7 +45,7 @@ template <typename T, int W, int PPT>
 __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     constexpr int m = W / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ float wmax[kPsThreads / 64];
+    __shared__ T wmax[kPsThreads / 64];
     const int4 item = a.items[xcd_item(blockIdx.x, gridDim.x)];
     for (int lo = item.y; lo < item.z; lo += kPsThreads * PPT) {
     __syncthreads();
@@ -70,7 +72,8 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
     T f0[PPT];
     int zlo[PPT], base[PPT], rot[PPT];
     c_t<T> v[PPT];
-    float amax = 0.f;
+    T amax = 0;             // the chunk's largest |Re f|, |Im f|, in f's precision
+    bool bad = false;       // a NaN or infinite value in the chunk
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int pk = lo + k * kPsThreads + threadIdx.x;
@@ -96,23 +99,32 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
                 rotate_rows<T, W, 16>(w1[k], rot[k]);
             }
             v[k] = ((const c_t<T> *)a.vals)[a.perm[pk]];
-            amax = fmaxf(amax, (float)fmax(fabs((double)v[k].x), fabs((double)v[k].y)));
+            if (!isfinite(v[k].x) || !isfinite(v[k].y)) {
+                bad = true;
+                v[k] = cmk<T>(0, 0);
+            }
+            amax = fmax(amax, fmax(fabs(v[k].x), fabs(v[k].y)));
         }
     }
     // chunk scale 2^ks: 2^ks max|f| < 2^53
-    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
     constexpr int NF = ps_nf<W>();
     int off[NF], lidx[NF];
     ps_offsets<NF>(a, it, m, off, lidx);
     c_t<T> *grid = (c_t<T> *)a.grid_out;
     const int64_t plane = (int64_t)a.n1 * a.n2;
-    __syncthreads();
-    float bmax = 0.f;
+    const bool chunk_bad = __syncthreads_or(bad);
+    T bmax = 0;
 #pragma unroll
-    for (int w = 0; w < kPsThreads / 64; ++w) bmax = fmaxf(bmax, wmax[w]);
+    for (int w = 0; w < kPsThreads / 64; ++w) bmax = fmax(bmax, wmax[w]);
+    // 2^ex > 1.0001 bmax (the margin covers window values a rounding above
+    // 1), taken without forming 1.0001 bmax, which could overflow
     int ex = 0;
-    if (bmax > 0.f) frexpf(bmax * 1.0001f, &ex);   // bmax < 2^ex (float rounding of |f| covered)
+    if (bmax > 0) {
+        const double mant = frexp((double)bmax, &ex);   // bmax = mant 2^ex, mant in [1/2, 1)
+        if (mant * 1.0001 >= 1.0) ++ex;
+    }
     const int ks = 53 - ex;
     double vr0[PPT], vi0[PPT];
 #pragma unroll
@@ -160,6 +172,11 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         }
         __syncthreads();
     }
+    // A NaN or infinite value was left out of the fixed-point sums; one NaN
+    // in the grid makes every coefficient of the adjoint NaN (the adjoint FFT
+    // sums every grid value into every coefficient), as the arithmetic would.
+    if (chunk_bad && threadIdx.x == 0)
+        unsafeAtomicAdd(&grid[(int64_t)wrapi(it.zbeg, a.n0) * plane + off[0]].x, (T)NAN);
     }
 }
 

@@ -364,6 +364,37 @@ def test_adjoint_dot_product_and_direct_sum(nf, N, dtype):
     assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (l2, li)
 
 
+@pytest.mark.parametrize("dtype,scales", [("c128", (1e-60, 1e-300, 1e300)), ("c64", (1e-30, 1e30))])
+def test_adjoint_extreme_values_and_nan(nf, dtype, scales):
+    """The adjoint's fixed-point accumulation takes its scale from each
+    chunk's largest value in f's own precision: values far from 1 (down to
+    1e-300, up to 1e300 in FP64) keep their relative accuracy against the
+    scaled direct adjoint; a NaN or infinite value makes the result NaN."""
+    import torch
+    N = (8, 10, 12)
+    m = 8 if dtype == "c128" else 4
+    x = rand_points(900, 43)
+    r = np.random.default_rng(44)
+    y = r.standard_normal(900) + 1j * r.standard_normal(900)
+    ref = oracle.ndft_adjoint(y, x, N)
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    for sc in scales:
+        log(f"adjoint scale {sc:g} {dtype}")
+        got = p.adjoint(to_dev(y * sc, dtype)).cpu().numpy().astype(np.complex128) / sc
+        l2, li = rel(got, ref)
+        assert np.all(np.isfinite(got)) and l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (sc, l2, li)
+    for bad in (float("nan"), float("inf")):
+        yb = y.copy()
+        yb[123] = bad
+        got = p.adjoint(to_dev(yb, dtype)).cpu().numpy()
+        assert np.all(np.isnan(got)), bad
+    # a finite call afterwards is unaffected
+    got = p.adjoint(to_dev(y, dtype)).cpu().numpy()
+    assert rel(got, ref)[0] <= tol(m, 2.0, dtype)
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------- grad ----
 
 @pytest.mark.parametrize("dtype", DTYPES)
