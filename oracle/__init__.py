@@ -11,6 +11,9 @@ Two parts:
   Sec. 2.2.1, evaluated in the one-loop order of eq. (Fs)), in C
   (``oracle/ndft.c``) with POSIX threads, reached through ctypes.  These are
   the reference every GPU result is compared with.
+* ``infftm_eval`` / ``infftm_coeffs`` / ``tube_refine`` -- the series of
+  eq. (fs) on a physical domain [a, b) (direct sums), the trapezoidal
+  coefficients of Sec. 2, and the vortex-tube refinement of Sec. 4.3.
 * ``rgrid_eval`` -- the series at a rectilinear grid as the nested per-axis
   sums of Sec. 2.1 (numpy FP64 matrix products with the E^d matrices).
 * ``oracle.nfft_steps`` -- a plain numpy FP64 statement of the windowed
@@ -192,6 +195,61 @@ def rgrid_eval(fhat: np.ndarray, y0, y1, y2) -> np.ndarray:
     t = (fhat.reshape(N0 * N1, N2) @ E2.T).reshape(N0, N1, M2)      # sum over k2
     t = np.matmul(E1[None, :, :], t)                                 # sum over k1: (N0, M1, M2)
     return (E0 @ t.reshape(N0, M1 * M2)).reshape(M0, M1, M2)        # sum over k0
+
+
+def infftm_eval(psihat: np.ndarray, a, b, xi: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """The truncated series of eq. (fs) on the domain prod [a_d, b_d) at points xi (M, 3):
+    psi(x) = sum_k psihat_k prod_d exp(+2 pi i k_d (x_d - a_d)/(b_d - a_d)) / sqrt(b_d - a_d),
+    k_d = i_d - N_d/2 for array index i_d (the paper's k_d - 1 - N_d/2).  The
+    direct sum: the NFFT-sign direct sum ``ndft_trafo`` at y = -(x - a)/(b - a)."""
+    a = np.asarray(a, dtype=np.float64).reshape(3)
+    b = np.asarray(b, dtype=np.float64).reshape(3)
+    xi = _points(xi)
+    y = -(xi - a[None, :]) / (b - a)[None, :]
+    return ndft_trafo(psihat, y, threads) / float(np.prod(np.sqrt(b - a)))
+
+
+def infftm_coeffs(psi: np.ndarray, a, b) -> np.ndarray:
+    """Coefficients of the samples psi on the regular grid X_N of the domain
+    (x_{d,n} = a_d + n h_d, h_d = (b_d - a_d)/N_d): the trapezoidal rule of
+    Sec. 2, psihat = fftshift(fftn(psi)) prod sqrt(b_d - a_d)/N_d."""
+    a = np.asarray(a, dtype=np.float64).reshape(3)
+    b = np.asarray(b, dtype=np.float64).reshape(3)
+    N = np.asarray(psi.shape)
+    return np.fft.fftshift(np.fft.fftn(psi)) * float(np.prod(np.sqrt(b - a) / N))
+
+
+def regular_grid(N, a, b) -> np.ndarray:
+    """The points of X_N (Sec. 2), (N0 N1 N2, 3) in C order of (n0, n1, n2)."""
+    a = np.asarray(a, dtype=np.float64).reshape(3)
+    b = np.asarray(b, dtype=np.float64).reshape(3)
+    g = [a[d] + np.arange(N[d]) * ((b[d] - a[d]) / N[d]) for d in range(3)]
+    G = np.meshgrid(*g, indexing="ij")
+    return np.stack([x.reshape(-1) for x in G], axis=1)
+
+
+def tube_refine(psihat: np.ndarray, a, b, rhobar) -> tuple[np.ndarray, np.ndarray, list]:
+    """Evaluation within vortex tubes (Sec. 4.3): start from the points of X_N
+    and rho = |psi|^2 there; for each threshold rhobar[l] keep the current
+    points with rho <= rhobar[l], replace each by the 27 points of a regular
+    grid of step h_d / 3^(l+1) centred on it, and evaluate rho there (direct
+    sums).  Returns (points, rho) of the last refined set and the number of
+    points kept at each level."""
+    a = np.asarray(a, dtype=np.float64).reshape(3)
+    b = np.asarray(b, dtype=np.float64).reshape(3)
+    N = psihat.shape
+    h = (b - a) / np.asarray(N)
+    pts = regular_grid(N, a, b)
+    rho = np.abs(infftm_eval(psihat, a, b, pts)) ** 2
+    kept = []
+    off = np.stack(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1], indexing="ij"), axis=-1).reshape(27, 3)
+    for lev, rb in enumerate(rhobar):
+        sel = pts[rho <= rb]
+        kept.append(int(sel.shape[0]))
+        step = h / 3.0 ** (lev + 1)
+        pts = (sel[:, None, :] + off[None, :, :] * step[None, None, :]).reshape(-1, 3)
+        rho = np.abs(infftm_eval(psihat, a, b, pts)) ** 2 if pts.shape[0] else np.zeros(0)
+    return pts, rho, kept
 
 
 def frequencies(Nd: int) -> np.ndarray:
