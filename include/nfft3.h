@@ -179,6 +179,43 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_
 int nfft3_batch_trafo_noalloc(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
                               void *const *out_dev, int deriv_mask);
 
+/* ---- The series on a physical domain (Sec. 2.2.1) and vortex tubes (Sec. 4.3)
+ * The paper's own form of the series, eq. (fs), on Omega = prod [a_d, b_d):
+ *
+ *     psi(xi) = sum_k psihat_k prod_d exp(+2 pi i k_d (xi_d - a_d)/(b_d - a_d)) / sqrt(b_d - a_d),
+ *
+ * k_d = i_d - N_d/2 for array index i_d (the paper's k_d - 1 - N_d/2 with
+ * 1-based k_d), psihat C-order (N0, N1, N2) with axis d paired with point
+ * column d.  As Sec. 2.2.1 does, it is evaluated as the NFFT problem at
+ * zeta_d = mod((xi_d - a_d)/(a_d - b_d), 1) - 1/2 with coefficients
+ * psihat_k (-1)^(k_0 + k_1 + k_2) / prod sqrt(b_d - a_d); both maps run on
+ * the device. */
+
+/* psi_dev[j] = psi(xi_j) for the M points xi_dev ((M, 3) FP64, physical
+ * coordinates; any finite values, the series being periodic on Omega) and
+ * coefficients psihat_dev (plan dtype); a_d < b_d (host arrays).  Sets the
+ * plan's points to the mapped xi (as nfft3_set_points, including its
+ * synchronisation and NFFT3_ERR_NONFINITE) and leaves them set; the mapped
+ * points and coefficients live in plan-owned scratch (allocated on first
+ * use, grown as needed). */
+int nfft3_infft3(nfft3_plan_t p, const double a[3], const double b[3], const void *psihat_dev, int64_t M,
+                 const double *xi_dev, void *psi_dev);
+
+/* Evaluation within vortex tubes (Sec. 4.3): start from the regular grid
+ * X_N of Omega (x_{d,n} = a_d + n h_d, h_d = (b_d - a_d)/N_d, n_d = 0 ..
+ * N_d - 1, in C order) and rho = |psi|^2 there; for l = 0 .. levels-1 keep
+ * the current points with rho <= rhobar[l] (host array) and replace each by
+ * the 27 points of the regular grid of step h_d / 3^(l+1) centred on it
+ * (neighbour (o0, o1, o2) in {-1, 0, 1}^3 at index 9(o0+1) + 3(o1+1) + o2+1,
+ * kept points in their order), evaluating rho there with nfft3_infft3.
+ * On return *count holds the number of points of the last set; they and
+ * their rho are copied to pts_dev ((cap, 3) FP64) and rho_dev (cap FP64)
+ * when count <= cap, else NFFT3_ERR_CAPACITY (nothing copied).  The plan's
+ * points are those of the last set afterwards.  Synchronises once per
+ * level (to size the next). */
+int nfft3_tube_refine(nfft3_plan_t p, const double a[3], const double b[3], const void *psihat_dev, int levels,
+                      const double *rhobar, int64_t cap, double *pts_dev, double *rho_dev, int64_t *count);
+
 /* ---- Evaluation at a rectilinear grid (Sec. 2.1) ---------------------------
  * The series at every point of a grid y0 x y1 x y2 with arbitrary (not
  * necessarily equispaced) coordinates per axis:

@@ -169,6 +169,64 @@ class Plan:
         check(lib.nfft3_grad_points(self._h, _ptr(fhat), _ptr(G), _ptr(out)), "nfft3_grad_points")
         return out
 
+    # -- the series on a physical domain (eq. (fs)) and vortex tubes ---------
+    @staticmethod
+    def _domain(a, b):
+        a = (ctypes.c_double * 3)(*[float(v) for v in a])
+        b = (ctypes.c_double * 3)(*[float(v) for v in b])
+        return a, b
+
+    def infft3(self, psihat: torch.Tensor, a, b, xi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """psi(xi) = sum_k psihat_k prod_d exp(2 pi i k_d (xi_d - a_d)/(b_d - a_d)) / sqrt(b_d - a_d)
+        at the (M, 3) float64 points xi of the domain prod [a_d, b_d); the
+        plan's points become the mapped xi."""
+        psihat = self._coeffs(psihat)
+        if xi.dim() != 2 or xi.shape[1] != 3 or xi.dtype != torch.float64 or xi.device != self.device:
+            raise TypeError("points must be (M, 3) float64 on the plan's device")
+        xi = xi.contiguous()
+        M = int(xi.shape[0])
+        if out is None:
+            out = torch.empty(M, dtype=self.dtype, device=self.device)
+        elif out.numel() != M or out.dtype != self.dtype or out.device != self.device:
+            raise ValueError(f"out must hold {M} {self.dtype} values on {self.device}")
+        self._out(out)
+        A, B = self._domain(a, b)
+        self._bind_stream()
+        self.epoch += 1
+        self.M = 0
+        check(lib.nfft3_infft3(self._h, A, B, _ptr(psihat), M, _ptr(xi), _ptr(out)), "nfft3_infft3")
+        self.M = M
+        return out
+
+    def tube_refine(self, psihat: torch.Tensor, a, b, rhobar: Sequence[float], cap: int | None = None):
+        """Evaluation within vortex tubes (Sec. 4.3): returns (points (K, 3)
+        float64, rho (K,) float64) of the last refined set."""
+        psihat = self._coeffs(psihat)
+        A, B = self._domain(a, b)
+        L = len(rhobar)
+        rb = (ctypes.c_double * max(L, 1))(*[float(v) for v in rhobar])
+        count = ctypes.c_int64(0)
+        self._bind_stream()
+        if cap is None:
+            n = self.N[0] * self.N[1] * self.N[2]
+            cap = n if L == 0 else 0        # first pass sizes the output
+        pts = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=self.device)
+        rho = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device)
+        self.epoch += 1
+        self.M = 0
+        code = lib.nfft3_tube_refine(self._h, A, B, _ptr(psihat), L, rb, int(cap), _ptr(pts), _ptr(rho),
+                                     ctypes.byref(count))
+        if code == -8:                      # capacity: size the output and run again
+            cap = int(count.value)
+            pts = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=self.device)
+            rho = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device)
+            code = lib.nfft3_tube_refine(self._h, A, B, _ptr(psihat), L, rb, int(cap), _ptr(pts), _ptr(rho),
+                                         ctypes.byref(count))
+        check(code, "nfft3_tube_refine")
+        K = int(count.value)
+        self.M = K
+        return pts[:K], rho[:K]
+
     # -- binning tuning ------------------------------------------------------
     def set_tuning(self, tile: int = 0, items: int = 0) -> None:
         """Tile edge (8/16/32 cells) and points per work item (256/512) of the

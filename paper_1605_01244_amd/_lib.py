@@ -58,6 +58,8 @@ def _load() -> ctypes.CDLL:
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),
         "nfft3_batch_trafo": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
         "nfft3_batch_trafo_noalloc": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
+        "nfft3_infft3": ([vp, dp, dp, vp, i64, vp, vp], ci),
+        "nfft3_tube_refine": ([vp, dp, dp, vp, ci, dp, i64, vp, vp, i64p], ci),
         "nfft3_rgrid_plan": ([ctypes.POINTER(vp), i64p, i64p, ci, vp], ci),
         "nfft3_rgrid_set_stream": ([vp, vp], ci),
         "nfft3_rgrid_set_axes": ([vp, vp, vp, vp], ci),

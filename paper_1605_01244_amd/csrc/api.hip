@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <new>
 
@@ -176,6 +177,7 @@ static void free_plan(nfft3_plan_impl *p) {
     (void)hipFree(p->flag);
     free_bins(p);
     (void)hipFree(p->sub.items);
+    free_infftm(p);
 }
 
 static int validate(const int64_t N[3], double sigma, int m, int dtype, int64_t n[3]) {
@@ -525,6 +527,35 @@ const char *nfft3_strerror(int code) {
 }
 
 const char *nfft3_last_hip_error(void) { return g_last_hip.c_str(); }
+
+// ---- the series on a physical domain (Sec. 2.2.1) and vortex tubes (Sec. 4.3)
+
+static bool domain_ok(const double a[3], const double b[3]) {
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(a[d]) || !std::isfinite(b[d]) || !(b[d] > a[d])) return false;
+    return true;
+}
+
+int nfft3_infft3(nfft3_plan_t p, const double a[3], const double b[3], const void *psihat, int64_t M, const double *xi,
+                 void *psi) {
+    if (!p || !a || !b || !psihat) return NFFT3_ERR_NULL;
+    if (M < 0 || M > (int64_t)INT32_MAX / 3) return NFFT3_ERR_INVALID_ARG;
+    if (M > 0 && (!xi || !psi)) return NFFT3_ERR_NULL;
+    if (!domain_ok(a, b)) return NFFT3_ERR_INVALID_ARG;
+    return launch_infft3(p, a, b, psihat, M, xi, psi);
+}
+
+int nfft3_tube_refine(nfft3_plan_t p, const double a[3], const double b[3], const void *psihat, int levels,
+                      const double *rhobar, int64_t cap, double *pts, double *rho, int64_t *count) {
+    if (!p || !a || !b || !psihat || !count) return NFFT3_ERR_NULL;
+    *count = 0;
+    if (levels < 0 || levels > 16 || cap < 0) return NFFT3_ERR_INVALID_ARG;
+    if (levels > 0 && !rhobar) return NFFT3_ERR_NULL;
+    if (cap > 0 && (!pts || !rho)) return NFFT3_ERR_NULL;
+    if (!domain_ok(a, b)) return NFFT3_ERR_INVALID_ARG;
+    if (p->N[0] * p->N[1] * p->N[2] > (int64_t)INT32_MAX / 3) return NFFT3_ERR_INVALID_ARG;
+    return launch_tube_refine(p, a, b, psihat, levels, rhobar, cap, pts, rho, count);
+}
 
 // ---- evaluation at a rectilinear grid (Sec. 2.1) ----------------------------
 

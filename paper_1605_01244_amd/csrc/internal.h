@@ -146,6 +146,18 @@ struct Subproblems {
     int64_t cap = 0;
 };
 
+// Scratch of the physical-domain calls (infftm.hip), grown as needed.
+struct InfftmScratch {
+    void *zeta = nullptr;  int64_t zeta_cap = 0;   // mapped points (doubles)
+    void *fhat = nullptr;  int64_t fhat_cap = 0;   // signed, scaled coefficients (elements)
+    void *pts = nullptr;   int64_t pts_cap = 0;    // tube: current points (doubles)
+    void *pts2 = nullptr;  int64_t pts2_cap = 0;   // tube: refined points (doubles)
+    void *psi = nullptr;   int64_t psi_cap = 0;    // tube: values (elements)
+    void *rho = nullptr;   int64_t rho_cap = 0;    // tube: |psi|^2 (doubles)
+    void *keep = nullptr;  int64_t keep_cap = 0;   // tube: flags and their scan (int pairs)
+    void *sums = nullptr;  int64_t sums_cap = 0;   // tube: block sums of the scan (ints)
+};
+
 struct nfft3_plan_impl {
     int dtype = NFFT3_C128;
     int m = 8;
@@ -183,6 +195,7 @@ struct nfft3_plan_impl {
     int tile_req = kMaxTile;  // requested tile edge (By, Bx may be smaller)
     Subproblems sub;
     int64_t epoch = 0;        // bumps at every set_points
+    InfftmScratch infftm;     // nfft3_infft3 / nfft3_tube_refine
 };
 
 // Evaluation at a rectilinear grid (Sec. 2.1): three complex matrix products.
@@ -254,6 +267,15 @@ int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);
 int launch_batch(int T, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out,
                  int deriv_mask, bool noalloc);
 
+// exclusive scan of n ints (in -> out, out[n] = total; in place allowed);
+// sums holds ceil(n / 1024) ints (points.hip)
+int launch_exclusive_scan(hipStream_t s, const int *in, int *out, int *sums, int64_t n);
+// physical domain and vortex tubes (infftm.hip)
+int launch_infft3(nfft3_plan_impl *p, const double a[3], const double b[3], const void *psihat, int64_t M,
+                  const double *xi, void *psi);
+int launch_tube_refine(nfft3_plan_impl *p, const double a[3], const double b[3], const void *psihat, int levels,
+                       const double *rhobar, int64_t cap, double *pts, double *rho, int64_t *count);
+void free_infftm(nfft3_plan_impl *p);
 // rectilinear grid (rgrid.hip)
 int launch_rgrid_axes(nfft3_rgrid_impl *g, const double *const y[3]);
 int launch_rgrid_eval(nfft3_rgrid_impl *g, const void *fhat, void *out);

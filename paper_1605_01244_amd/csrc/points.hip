@@ -127,6 +127,11 @@ __global__ void add_block_offsets_kernel(int *__restrict__ out, const int *__res
 
 // exclusive scan of n ints (in -> out), out[n] = total; sums needs ceil(n/1024) ints
 static int exclusive_scan(hipStream_t s, const int *in, int *out, int *sums, int64_t n) {
+    if (n <= 0) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, out, (int64_t)1, 0);
+        NFFT3_LAUNCH_CHECK("fill_int_kernel");
+        return NFFT3_OK;
+    }
     const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, sums, n);
     NFFT3_LAUNCH_CHECK("scan_blocks_kernel");
@@ -149,6 +154,10 @@ scatter_kernel(const double *__restrict__ x, int64_t M, const int *__restrict__ 
     xs[3 * pos + 1] = fold_unit(xp[1]);
     xs[3 * pos + 2] = fold_unit(xp[2]);
     perm[pos] = (int)j;
+}
+
+int launch_exclusive_scan(hipStream_t s, const int *in, int *out, int *sums, int64_t n) {
+    return exclusive_scan(s, in, out, sums, n);
 }
 
 // ---- two-level counting sort (tile, then z within the tile) ---------------
