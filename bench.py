@@ -151,7 +151,7 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint / point-gradient / batched / autograd measurements")
-    ap.add_argument("--only", choices=["batched", "autograd", "rectilinear"], default=None,
+    ap.add_argument("--only", choices=["batched", "autograd", "rectilinear", "gpe"], default=None,
                     help="run only this extra workload and print its result (profiling runs)")
     return ap.parse_args()
 
@@ -279,6 +279,47 @@ def bench_rgrid(nf, torch, dev, workloads, stream):
     return res
 
 
+def bench_gpe_tube(nf, torch, dev, workloads, stream):
+    """The paper's pipeline of Sec. 5 on its grid: Strang steps of the GPE
+    (N = 80^3 on [-20, 60)^3, tau = 0.1, 200 steps to T = 20) from two
+    straight vortices, then the state's coefficients and the evaluation
+    within vortex tubes (rho <= 0.2, then 0.05) on the physical domain.
+    Times from HIP events; FP64 and FP32."""
+    N, a, b = 80, -20.0, 60.0
+    psi0 = workloads.gpe_two_vortices(N, a, b)
+    res = {"workload": "GPE Strang splitting, 80^3 on [-20,60)^3, tau=0.1, 200 steps; then vortex-tube "
+                       "evaluation rho <= 0.2, 0.05 of the final state"}
+    A3, B3 = [a] * 3, [b] * 3
+    for form, dt, m in (("fp64", torch.complex128, 8), ("fp32", torch.complex64, 4)):
+        g = nf.GPE((N, N, N), A3, B3, dtype=dt, device=dev)
+        g.set_state(torch.from_numpy(psi0).to(dev).to(dt))
+        g.step(0.1, 2)
+        g.set_state(torch.from_numpy(psi0).to(dev).to(dt))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(0.1, 200)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        ph = g.coeffs()
+        plan = nf.Plan((N, N, N), m=m, dtype=dt, device=dev)
+        plan.tube_refine(ph, A3, B3, [0.2, 0.05])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pts, rho = plan.tube_refine(ph, A3, B3, [0.2, 0.05])
+        torch.cuda.synchronize()
+        t_tube = time.perf_counter() - t0
+        res[form] = {"m": m, "gpe_ms_per_step": ms / 200, "gpe_ms_total": ms, "tube_ms": t_tube * 1e3,
+                     "tube_points": int(pts.shape[0])}
+        log(f"gpe {form}: {ms / 200:.3f} ms per step; tube refinement {t_tube * 1e3:.1f} ms, "
+            f"{pts.shape[0]} points")
+        plan.close()
+        g.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_autograd(nf, torch, dev, workloads):
     """Differentiation form: N = 128^3, M = 1e6 clustered points; forward
     (set_points + trafo) and backward (adjoint + point gradient) of
@@ -331,6 +372,8 @@ def main():
             res = bench_batched(nf, torch, dev, workloads, stream)
         elif args.only == "rectilinear":
             res = bench_rgrid(nf, torch, dev, workloads, stream)
+        elif args.only == "gpe":
+            res = bench_gpe_tube(nf, torch, dev, workloads, stream)
         else:
             res = bench_autograd(nf, torch, dev, workloads)
         print(json.dumps({args.only: res}), flush=True)
@@ -415,6 +458,7 @@ def main():
         extras["batched"] = bench_batched(nf, torch, dev, workloads, stream)
         extras["autograd"] = bench_autograd(nf, torch, dev, workloads)
         extras["rectilinear"] = bench_rgrid(nf, torch, dev, workloads, stream)
+        extras["gpe_tube"] = bench_gpe_tube(nf, torch, dev, workloads, stream)
 
     # CPU baseline = the oracle on the seeded sample (also the error reference)
     cpu = None

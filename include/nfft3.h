@@ -216,6 +216,35 @@ int nfft3_infft3(nfft3_plan_t p, const double a[3], const double b[3], const voi
 int nfft3_tube_refine(nfft3_plan_t p, const double a[3], const double b[3], const void *psihat_dev, int levels,
                       const double *rhobar, int64_t cap, double *pts_dev, double *rho_dev, int64_t *count);
 
+/* ---- Gross-Pitaevskii time splitting (Sec. 3.1) ----------------------------
+ * d psi/dt = (i/2) Lap psi + (i/2)(1 - |psi|^2) psi on the regular grid X_N
+ * of the periodic domain prod [a_d, b_d) (x_{d,n} = a_d + n h_d), by Strang
+ * splitting: half a step of the potential part (exact: it keeps |psi|), a
+ * full step of the kinetic part (exact in Fourier space: mode k times
+ * exp(-i tau |kappa_k|^2 / 2), kappa_{k,d} = 2 pi k_d / (b_d - a_d)), half a
+ * step of the potential part; consecutive half steps are merged.  The
+ * Fourier transforms are the library's Stockham passes, in place. */
+typedef struct nfft3_gpe_s *nfft3_gpe_t;
+
+/* N_d even, 16 <= N_d <= 2048, prime factors 2, 3, 5, 7 (e.g. the paper's
+ * 80); a_d < b_d (host arrays).  Allocates the state and one scratch of
+ * N0 N1 N2 complex values. */
+int nfft3_gpe_create(nfft3_gpe_t *out, const int64_t N[3], const double a[3], const double b[3], int dtype,
+                     void *stream);
+int nfft3_gpe_set_stream(nfft3_gpe_t g, void *stream);
+/* Copy the state from / to psi_dev (N0 N1 N2 complex, C order of (n0, n1, n2)). */
+int nfft3_gpe_set_state(nfft3_gpe_t g, const void *psi_dev);
+int nfft3_gpe_get_state(nfft3_gpe_t g, void *psi_dev);
+/* nsteps Strang steps of size tau (any sign: the scheme is time
+ * reversible).  Does not synchronise. */
+int nfft3_gpe_step(nfft3_gpe_t g, double tau, int nsteps);
+/* The state's coefficients by the trapezoidal rule of Sec. 2,
+ * psihat = fftshift(fftn(psi)) prod sqrt(b_d - a_d) / N_d, in the layout of
+ * nfft3_infft3 (C order, index i_d <-> frequency i_d - N_d/2): a time
+ * snapshot ready for nfft3_infft3 / nfft3_tube_refine / the batched form. */
+int nfft3_gpe_coeffs(nfft3_gpe_t g, void *psihat_dev);
+int nfft3_gpe_destroy(nfft3_gpe_t g);
+
 /* ---- Evaluation at a rectilinear grid (Sec. 2.1) ---------------------------
  * The series at every point of a grid y0 x y1 x y2 with arbitrary (not
  * necessarily equispaced) coordinates per axis:

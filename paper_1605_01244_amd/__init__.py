@@ -26,7 +26,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 from ._lib import NFFT3_C64, NFFT3_C128, NFFT3Error, check, lib
 
-__all__ = ["Plan", "RectGrid", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error"]
+__all__ = ["Plan", "RectGrid", "GPE", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error"]
 
 _DT = {torch.complex64: NFFT3_C64, torch.complex128: NFFT3_C128}
 
@@ -291,6 +291,69 @@ class Plan:
         g = g.contiguous()
         self._bind_stream()
         check(lib.nfft3_grid_copy(self._h, _ptr(g), 1), "nfft3_grid_copy")
+
+
+class GPE:
+    """Strang splitting of the Gross-Pitaevskii equation (Sec. 3.1) on the
+    regular grid of the periodic domain prod [a_d, b_d): state psi (N0, N1,
+    N2) complex on the device; step(tau, n); coeffs() gives the trapezoidal
+    coefficients of the state for Plan.infft3 / tube_refine."""
+
+    def __init__(self, N: Sequence[int], a, b, dtype: torch.dtype = torch.complex128, device=None):
+        if dtype not in _DT:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.N = tuple(int(v) for v in N)
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        A = (ctypes.c_double * 3)(*[float(v) for v in a])
+        B = (ctypes.c_double * 3)(*[float(v) for v in b])
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(lib.nfft3_gpe_create(ctypes.byref(self._h), (ctypes.c_int64 * 3)(*self.N), A, B, _DT[dtype],
+                                       ctypes.c_void_p(stream)), "nfft3_gpe_create")
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib.nfft3_gpe_set_stream(self._h, ctypes.c_void_p(s)), "nfft3_gpe_set_stream")
+
+    def _grid(self, t: torch.Tensor) -> torch.Tensor:
+        if tuple(t.shape) != self.N or t.dtype != self.dtype or t.device != self.device:
+            raise ValueError(f"state must be {self.N} {self.dtype} on {self.device}")
+        return t.contiguous()
+
+    def set_state(self, psi: torch.Tensor) -> None:
+        psi = self._grid(psi)
+        self._bind_stream()
+        check(lib.nfft3_gpe_set_state(self._h, _ptr(psi)), "nfft3_gpe_set_state")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def state(self) -> torch.Tensor:
+        out = torch.empty(self.N, dtype=self.dtype, device=self.device)
+        self._bind_stream()
+        check(lib.nfft3_gpe_get_state(self._h, _ptr(out)), "nfft3_gpe_get_state")
+        return out
+
+    def step(self, tau: float, nsteps: int = 1) -> None:
+        self._bind_stream()
+        check(lib.nfft3_gpe_step(self._h, float(tau), int(nsteps)), "nfft3_gpe_step")
+
+    def coeffs(self) -> torch.Tensor:
+        out = torch.empty(self.N, dtype=self.dtype, device=self.device)
+        self._bind_stream()
+        check(lib.nfft3_gpe_coeffs(self._h, _ptr(out)), "nfft3_gpe_coeffs")
+        return out
+
+    def close(self):
+        if self._h:
+            lib.nfft3_gpe_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class RectGrid:

@@ -60,6 +60,13 @@ def _load() -> ctypes.CDLL:
         "nfft3_batch_trafo_noalloc": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
         "nfft3_infft3": ([vp, dp, dp, vp, i64, vp, vp], ci),
         "nfft3_tube_refine": ([vp, dp, dp, vp, ci, dp, i64, vp, vp, i64p], ci),
+        "nfft3_gpe_create": ([ctypes.POINTER(vp), i64p, dp, dp, ci, vp], ci),
+        "nfft3_gpe_set_stream": ([vp, vp], ci),
+        "nfft3_gpe_set_state": ([vp, vp], ci),
+        "nfft3_gpe_get_state": ([vp, vp], ci),
+        "nfft3_gpe_step": ([vp, ctypes.c_double, ci], ci),
+        "nfft3_gpe_coeffs": ([vp, vp], ci),
+        "nfft3_gpe_destroy": ([vp], ci),
         "nfft3_rgrid_plan": ([ctypes.POINTER(vp), i64p, i64p, ci, vp], ci),
         "nfft3_rgrid_set_stream": ([vp, vp], ci),
         "nfft3_rgrid_set_axes": ([vp, vp, vp, vp], ci),

@@ -528,6 +528,118 @@ const char *nfft3_strerror(int code) {
 
 const char *nfft3_last_hip_error(void) { return g_last_hip.c_str(); }
 
+// ---- Gross-Pitaevskii time splitting (Sec. 3.1) --------------------------------
+
+static void free_gpe(nfft3_gpe_impl *g) {
+    for (int d = 0; d < 3; ++d) {
+        (void)hipFree(g->fp.cdec[d]);
+        (void)hipFree(g->fp.fft[d].tw);
+        (void)hipFree(g->fp.fft[d].stw);
+        g->fp.cdec[d] = g->fp.fft[d].tw = g->fp.fft[d].stw = nullptr;
+    }
+    (void)hipFree(g->state);
+    (void)hipFree(g->work);
+    g->state = g->work = nullptr;
+}
+
+static int build_gpe(nfft3_gpe_impl *g) {
+    nfft3_plan_impl *p = &g->fp;
+    const bool f64 = p->dtype == NFFT3_C128;
+    NFFT3_HIP_TRY(hipGetDevice(&p->device));
+    for (int d = 0; d < 3; ++d) {
+        std::vector<double> ones((size_t)p->N[d], 1.0);
+        int rc = f64 ? upload_real<double>(ones, &p->cdec[d]) : upload_real<float>(ones, &p->cdec[d]);
+        if (rc) return rc;
+        std::vector<int> rad;
+        factor_radices((int)p->n[d], rad);
+        p->fft[d].n = (int)p->n[d];
+        p->fft[d].nrad = (int)rad.size();
+        for (size_t i = 0; i < rad.size(); ++i) p->fft[d].radix[i] = rad[i];
+        rc = f64 ? upload_twiddles<double>((int)p->n[d], &p->fft[d].tw)
+                 : upload_twiddles<float>((int)p->n[d], &p->fft[d].tw);
+        if (rc) return rc;
+        rc = f64 ? upload_stage_twiddles<double>((int)p->n[d], &p->fft[d].stw)
+                 : upload_stage_twiddles<float>((int)p->n[d], &p->fft[d].stw);
+        if (rc) return rc;
+    }
+    const size_t bytes = (size_t)p->N[0] * p->N[1] * p->N[2] * p->elt;
+    NFFT3_HIP_TRY(hipMalloc(&g->state, bytes));
+    NFFT3_HIP_TRY(hipMalloc(&g->work, bytes));
+    return NFFT3_OK;
+}
+
+int nfft3_gpe_create(nfft3_gpe_t *out, const int64_t N[3], const double a[3], const double b[3], int dtype,
+                     void *stream) {
+    if (!out) return NFFT3_ERR_NULL;
+    *out = nullptr;
+    if (!N || !a || !b) return NFFT3_ERR_NULL;
+    if (dtype != NFFT3_C64 && dtype != NFFT3_C128) return NFFT3_ERR_DTYPE;
+    for (int d = 0; d < 3; ++d) {
+        std::vector<int> rad;
+        // at least two radix stages per axis (the passes run in place)
+        if (N[d] < 16 || N[d] > 2048 || N[d] % 2 || !factor_radices((int)N[d], rad)) return NFFT3_ERR_INVALID_ARG;
+        if (!std::isfinite(a[d]) || !std::isfinite(b[d]) || !(b[d] > a[d])) return NFFT3_ERR_INVALID_ARG;
+    }
+    auto *g = new (std::nothrow) nfft3_gpe_s();
+    if (!g) return NFFT3_ERR_OOM;
+    g->fp.dtype = dtype;
+    g->fp.elt = dtype == NFFT3_C128 ? 16 : 8;
+    g->fp.sigma = 1.0;
+    g->fp.stream = (hipStream_t)stream;
+    for (int d = 0; d < 3; ++d) {
+        g->fp.N[d] = g->fp.n[d] = N[d];
+        g->len[d] = b[d] - a[d];
+    }
+    const int rc = build_gpe(g);
+    if (rc) {
+        free_gpe(g);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return NFFT3_OK;
+}
+
+int nfft3_gpe_set_stream(nfft3_gpe_t g, void *stream) {
+    if (!g) return NFFT3_ERR_NULL;
+    g->fp.stream = (hipStream_t)stream;
+    return NFFT3_OK;
+}
+
+int nfft3_gpe_set_state(nfft3_gpe_t g, const void *psi) {
+    if (!g || !psi) return NFFT3_ERR_NULL;
+    const size_t bytes = (size_t)g->fp.N[0] * g->fp.N[1] * g->fp.N[2] * g->fp.elt;
+    NFFT3_HIP_TRY(hipMemcpyAsync(g->state, psi, bytes, hipMemcpyDeviceToDevice, g->fp.stream));
+    return NFFT3_OK;
+}
+
+int nfft3_gpe_get_state(nfft3_gpe_t g, void *psi) {
+    if (!g || !psi) return NFFT3_ERR_NULL;
+    const size_t bytes = (size_t)g->fp.N[0] * g->fp.N[1] * g->fp.N[2] * g->fp.elt;
+    NFFT3_HIP_TRY(hipMemcpyAsync(psi, g->state, bytes, hipMemcpyDeviceToDevice, g->fp.stream));
+    return NFFT3_OK;
+}
+
+int nfft3_gpe_step(nfft3_gpe_t g, double tau, int nsteps) {
+    if (!g) return NFFT3_ERR_NULL;
+    if (nsteps < 0 || !std::isfinite(tau)) return NFFT3_ERR_INVALID_ARG;
+    g->tau = tau;
+    return launch_gpe_steps(g, nsteps);
+}
+
+int nfft3_gpe_coeffs(nfft3_gpe_t g, void *psihat) {
+    if (!g || !psihat) return NFFT3_ERR_NULL;
+    return launch_gpe_coeffs(g, psihat);
+}
+
+int nfft3_gpe_destroy(nfft3_gpe_t g) {
+    if (!g) return NFFT3_OK;
+    if (g->fp.stream) (void)hipStreamSynchronize(g->fp.stream);
+    free_gpe(g);
+    delete g;
+    return NFFT3_OK;
+}
+
 // ---- the series on a physical domain (Sec. 2.2.1) and vortex tubes (Sec. 4.3)
 
 static bool domain_ok(const double a[3], const double b[3]) {

@@ -215,6 +215,16 @@ struct nfft3_rgrid_impl {
     bool have_axes = false;
 };
 
+// Gross-Pitaevskii time splitting (gpe.hip): an FFT-only plan (n = N, unit
+// deconvolution factors) whose grid passes transform the state in place.
+struct nfft3_gpe_impl {
+    nfft3_plan_impl fp;
+    void *state = nullptr;      // psi on X_N (N0 N1 N2 complex, C order)
+    void *work = nullptr;       // coefficient output scratch
+    double tau = 0.0;
+    double len[3] = {0, 0, 0};  // b_d - a_d
+};
+
 // Raise a kernel's dynamic-LDS limit above the 64 KiB default when needed.
 void allow_lds(const void *kernel, size_t bytes);
 
@@ -276,6 +286,9 @@ int launch_infft3(nfft3_plan_impl *p, const double a[3], const double b[3], cons
 int launch_tube_refine(nfft3_plan_impl *p, const double a[3], const double b[3], const void *psihat, int levels,
                        const double *rhobar, int64_t cap, double *pts, double *rho, int64_t *count);
 void free_infftm(nfft3_plan_impl *p);
+// GPE time splitting (gpe.hip)
+int launch_gpe_steps(nfft3_gpe_impl *g, int nsteps);
+int launch_gpe_coeffs(nfft3_gpe_impl *g, void *psihat);
 // rectilinear grid (rgrid.hip)
 int launch_rgrid_axes(nfft3_rgrid_impl *g, const double *const y[3]);
 int launch_rgrid_eval(nfft3_rgrid_impl *g, const void *fhat, void *out);
@@ -284,3 +297,4 @@ int launch_rgrid_eval(nfft3_rgrid_impl *g, const void *fhat, void *out);
 
 struct nfft3_plan_s : nfft3::nfft3_plan_impl {};
 struct nfft3_rgrid_s : nfft3::nfft3_rgrid_impl {};
+struct nfft3_gpe_s : nfft3::nfft3_gpe_impl {};

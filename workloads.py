@@ -26,6 +26,8 @@ i - N/2; points are (M, 3) in the unit box [-1/2, 1/2)^3):
 * ``subbox_grid_points`` -- a fine regular grid in a small sub-box around the
   closest approach of the two lines (the localised high-resolution
   evaluation of Sec. 5).
+* ``gpe_two_vortices`` -- the initial state of the reconnection run of Sec. 5
+  (two straight vortices with a tanh core) on its 80^3 grid.
 """
 from __future__ import annotations
 
@@ -200,6 +202,26 @@ def subbox_grid_points(vp: VortexPair, fine: int = 128, width: float = 1.0 / 16)
 def coarse_index_of(points_unit: np.ndarray, N: int) -> np.ndarray:
     """Integer coarse-node index (i0, i1, i2) of points lying on coarse nodes."""
     return np.mod(np.rint((points_unit + 0.5) * N).astype(np.int64), N)
+
+
+def gpe_two_vortices(N: int = 80, a: float = -20.0, b: float = 60.0) -> np.ndarray:
+    """Initial state of the reconnection run of Sec. 5 on the regular grid of
+    [a, b)^3: the product of two straight vortices, one through (2, 0, 0)
+    along (0, 1, 0), one through (-2, 0, 0) along (0, 0, 1), each with the
+    tanh(r / sqrt 2) core (the paper's Pade core profile is not given), the
+    distance to each line taken to its nearest periodic image."""
+    L = b - a
+    g = a + np.arange(N) * (L / N)
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1)
+    psi = np.ones((N, N, N), dtype=np.complex128)
+    for p0, u, sgn in ((np.array([2.0, 0.0, 0.0]), 1, 1), (np.array([-2.0, 0.0, 0.0]), 2, 1)):
+        rel = X - p0
+        rel = rel - L * np.round(rel / L)
+        axes = [d for d in range(3) if d != u]
+        a1, a2 = rel[..., axes[0]], rel[..., axes[1]]
+        r = np.sqrt(a1 * a1 + a2 * a2)
+        psi *= np.tanh(r / math.sqrt(2.0)) * np.exp(1j * sgn * np.arctan2(a2, a1))
+    return psi
 
 
 # ---------------------------------------------------------------------------
