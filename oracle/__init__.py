@@ -18,6 +18,9 @@ Two parts:
   with numpy's FFT.
 * ``rgrid_eval`` -- the series at a rectilinear grid as the nested per-axis
   sums of Sec. 2.1 (numpy FP64 matrix products with the E^d matrices).
+* ``ndft_lowdim*`` / ``infft_lowdim`` / ``rgrid_lowdim`` -- the one- and
+  two-dimensional series (Appendix B: the E psihat product, infft, infft2,
+  igridft2) as numpy FP64 products with the per-axis phase matrices.
 * ``oracle.nfft_steps`` -- a plain numpy FP64 statement of the windowed
   algorithm the GPU implements (deconvolve, oversampled FFT, window sum),
   used to check the GPU stages one at a time.
@@ -197,6 +200,81 @@ def rgrid_eval(fhat: np.ndarray, y0, y1, y2) -> np.ndarray:
     t = (fhat.reshape(N0 * N1, N2) @ E2.T).reshape(N0, N1, M2)      # sum over k2
     t = np.matmul(E1[None, :, :], t)                                 # sum over k1: (N0, M1, M2)
     return (E0 @ t.reshape(N0, M1 * M2)).reshape(M0, M1, M2)        # sum over k0
+
+
+def _lowdim(fhat, x):
+    fhat = np.asarray(fhat, dtype=np.complex128)
+    d = fhat.ndim
+    if d not in (1, 2) or any(n < 2 or n % 2 for n in fhat.shape):
+        raise ValueError("coefficients must be a 1-D or 2-D array of even sizes >= 2")
+    x = np.asarray(x, dtype=np.float64).reshape(-1, d)
+    return fhat, x, d
+
+
+def ndft_lowdim(fhat: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """f_j = sum_k fhat_k exp(-2 pi i k.x_j) for a one- or two-dimensional
+    coefficient array (index i <-> frequency i - N/2) at points x (M, d).
+    One dimension: the matrix-vector product E fhat that Appendix B writes
+    out for this case, E[j, k] = exp(-2 pi i k x_j).  Two dimensions: that
+    product along axis 1 for every k0 row, then the sum over k0 with the
+    axis-0 phases.  FP64."""
+    fhat, x, d = _lowdim(fhat, x)
+    if d == 1:
+        return axis_phases(fhat.shape[0], x[:, 0]) @ fhat
+    E0 = axis_phases(fhat.shape[0], x[:, 0])              # (M, N0)
+    E1 = axis_phases(fhat.shape[1], x[:, 1])              # (M, N1)
+    inner = E1 @ fhat.T                                   # (M, N0): sum over k1
+    return np.sum(E0 * inner, axis=1)                     # sum over k0
+
+
+def ndft_lowdim_adjoint(f: np.ndarray, x: np.ndarray, N) -> np.ndarray:
+    """fhat_k = sum_j f_j exp(+2 pi i k.x_j) (the conjugate transpose of
+    ``ndft_lowdim``) for N of one or two entries."""
+    N = tuple(int(v) for v in np.atleast_1d(N))
+    _, x, d = _lowdim(np.zeros(N), x)
+    f = np.asarray(f, dtype=np.complex128).reshape(-1)
+    if d == 1:
+        return np.conj(axis_phases(N[0], x[:, 0])).T @ f
+    E0 = np.conj(axis_phases(N[0], x[:, 0]))
+    E1 = np.conj(axis_phases(N[1], x[:, 1]))
+    return (E0 * f[:, None]).T @ E1
+
+
+def ndft_lowdim_grad(fhat: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """df_j/dx_{j,d} = sum_k (-2 pi i k_d) fhat_k exp(-2 pi i k.x_j), (M, d) complex."""
+    fhat, x, d = _lowdim(fhat, x)
+    cols = []
+    for ax in range(d):
+        k = frequencies(fhat.shape[ax]).astype(np.float64)
+        shape = [1] * d
+        shape[ax] = -1
+        cols.append(ndft_lowdim(fhat * (-2j * np.pi * k.reshape(shape)), x))
+    return np.stack(cols, axis=1)
+
+
+def infft_lowdim(psihat: np.ndarray, a, b, xi: np.ndarray) -> np.ndarray:
+    """The one- or two-dimensional series on prod [a_d, b_d) (Appendix B's
+    infft / infft2): psi(x) = sum_k psihat_k prod_d exp(+2 pi i k_d (x_d - a_d)
+    /(b_d - a_d)) / sqrt(b_d - a_d), as ``ndft_lowdim`` at y = -(x - a)/(b - a)."""
+    psihat, xi, d = _lowdim(psihat, xi)
+    a = np.asarray(a, dtype=np.float64).reshape(d)
+    b = np.asarray(b, dtype=np.float64).reshape(d)
+    y = -(xi - a[None, :]) / (b - a)[None, :]
+    return ndft_lowdim(psihat, y) / float(np.prod(np.sqrt(b - a)))
+
+
+def rgrid_lowdim(fhat: np.ndarray, *ys) -> np.ndarray:
+    """The series at a one- or two-dimensional rectilinear grid: E0 fhat
+    (one dimension, the matrix-vector product of Appendix B) or E0 fhat E1^T
+    (two dimensions, the double matrix product of igridft2), E_d[i, k] =
+    exp(-2 pi i k y_d[i])."""
+    fhat = np.asarray(fhat, dtype=np.complex128)
+    if fhat.ndim != len(ys) or fhat.ndim not in (1, 2):
+        raise ValueError("one coordinate vector per axis, one or two axes")
+    E = [axis_phases(n, y) for n, y in zip(fhat.shape, ys)]
+    if fhat.ndim == 1:
+        return E[0] @ fhat
+    return E[0] @ fhat @ E[1].T
 
 
 def infftm_eval(psihat: np.ndarray, a, b, xi: np.ndarray, threads: int | None = None) -> np.ndarray:
