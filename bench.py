@@ -151,7 +151,7 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint / point-gradient / batched / autograd measurements")
-    ap.add_argument("--only", choices=["batched", "autograd", "rectilinear", "gpe"], default=None,
+    ap.add_argument("--only", choices=["batched", "autograd", "rectilinear", "gpe", "lowdim"], default=None,
                     help="run only this extra workload and print its result (profiling runs)")
     return ap.parse_args()
 
@@ -279,6 +279,43 @@ def bench_rgrid(nf, torch, dev, workloads, stream):
     return res
 
 
+def bench_lowdim(nf, torch, dev, workloads, stream):
+    """One- and two-dimensional plans (Appendix B's infft / infft2): N = 1024
+    and 1024^2 |k|^-2 coefficients at M = 1e7 uniform points; per form the
+    median event time of nfft3_trafo, its stages, and the window sums' HBM
+    rate (algorithmic bytes: the grid once, 28 B per point for its sorted
+    coordinates and index, the result)."""
+    res = {}
+    M = 10_000_000
+    for d, N in ((1, 1024), (2, 1024)):
+        fh, x = workloads.lowdim_case(d, N, M)
+        xd = torch.from_numpy(x).to(dev)
+        name = f"{d}-D N={N}^{d}" if d > 1 else f"1-D N={N}"
+        entry = {"N": [N] * d, "M": M}
+        for form, dt, m in (("fp64", torch.complex128, 8), ("fp32", torch.complex64, 4)):
+            plan = nf.Plan((N,) * d, m=m, dtype=dt, device=dev)
+            plan.set_points(xd)
+            fd = torch.from_numpy(fh).to(dev).to(dt)
+            out = torch.empty(M, dtype=dt, device=dev)
+            plan.trafo(fd, out=out)
+            ms = median(event_times(torch, stream, lambda: plan.trafo(fd, out=out), 10)[0])
+            ms_grid = median(event_times(torch, stream, lambda: plan.stage_grid(fd), 10)[0])
+            ms_interp = median(event_times(torch, stream, lambda: plan.stage_interp(out), 10)[0])
+            elt = 16 if form == "fp64" else 8
+            alg = float(np.prod(plan.n)) * elt + M * (28 + elt)
+            gbs = alg / (ms_interp * 1e-3) / 1e9
+            entry[form] = {"m": m, "ms": ms, "points_per_s": M / (ms * 1e-3), "ms_grid_stage": ms_grid,
+                           "ms_interp_stage": ms_interp, "interp_gbs": gbs, "interp_hbm_frac": gbs / HBM_PEAK_GBS}
+            log(f"{name} {form}: {ms:.3f} ms ({M / ms * 1e3:.3e} pts/s), grid {ms_grid:.3f} ms, "
+                f"window sums {ms_interp:.3f} ms ({gbs:.0f} GB/s)")
+            plan.close()
+            del out, fd
+        res[name] = entry
+        del xd
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_gpe_tube(nf, torch, dev, workloads, stream):
     """The paper's pipeline of Sec. 5 on its grid: Strang steps of the GPE
     (N = 80^3 on [-20, 60)^3, tau = 0.1, 200 steps to T = 20) from two
@@ -374,6 +411,8 @@ def main():
             res = bench_rgrid(nf, torch, dev, workloads, stream)
         elif args.only == "gpe":
             res = bench_gpe_tube(nf, torch, dev, workloads, stream)
+        elif args.only == "lowdim":
+            res = bench_lowdim(nf, torch, dev, workloads, stream)
         else:
             res = bench_autograd(nf, torch, dev, workloads)
         print(json.dumps({args.only: res}), flush=True)
@@ -459,6 +498,7 @@ def main():
         extras["autograd"] = bench_autograd(nf, torch, dev, workloads)
         extras["rectilinear"] = bench_rgrid(nf, torch, dev, workloads, stream)
         extras["gpe_tube"] = bench_gpe_tube(nf, torch, dev, workloads, stream)
+        extras["lowdim"] = bench_lowdim(nf, torch, dev, workloads, stream)
 
     # CPU baseline = the oracle on the seeded sample (also the error reference)
     cpu = None

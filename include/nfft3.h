@@ -69,7 +69,12 @@ enum nfft3_status {
 };
 
 /* Create a plan for coefficient sizes N[0..2] (host array).
- *   N_d    even, 2 <= N_d (the set I_N of Sec. 2 needs N_d even).
+ *   N_d    even, 2 <= N_d (the set I_N of Sec. 2 needs N_d even); or
+ *          N_0 = 1, or N_0 = N_1 = 1: leading unit axes, whose only frequency
+ *          is 0, so the sum over them is exact (no oversampling, no window:
+ *          n_d = 1).  Such a plan is the two- or one-dimensional transform
+ *          with points still (M, 3) (unit coordinates are ignored); see
+ *          nfft3_plan_nd for the same with (M, d) points.
  *   sigma  oversampling factor > 1; n_d = sigma * N_d must be an even integer
  *          whose prime factors are 2, 3, 5 and 7, with n_d <= 2048.
  *   m      window half-width in oversampled cells, 1 <= m <= 10, 2m <= n_d.
@@ -83,6 +88,21 @@ enum nfft3_status {
  * device. */
 int nfft3_plan(nfft3_plan_t *out, const int64_t N[3], double sigma, int m, int dtype,
                void *stream);
+
+/* Plan of d = 1, 2 or 3 axes (the one- and two-dimensional series the paper
+ * evaluates with infft and infft2, Appendix B): N[0..d-1] (host array), each
+ * even and >= 2, is the coefficient array's shape; the plan is the 3-D plan
+ * of nfft3_plan with 3 - d leading unit axes, so the other arguments,
+ * limits and errors are those of nfft3_plan.  On such a plan
+ *   - points are (M, d) FP64 arrays (nfft3_set_points,
+ *     nfft3_points_unchanged; widened on the device into a plan buffer),
+ *   - nfft3_grad_points writes (M, d) components,
+ *   - bit i of a derivative mask (nfft3_trafo_fields) is the plan's axis i,
+ *   - nfft3_infft3 takes a[d], b[d] and (M, d) points,
+ *   - nfft3_tube_refine and nfft3_batch_trafo return NFFT3_ERR_INVALID_ARG
+ *     (three-dimensional plans only). */
+int nfft3_plan_nd(nfft3_plan_t *out, int d, const int64_t *N, double sigma, int m, int dtype,
+                  void *stream);
 
 /* Rebind the plan to another stream of the same device. */
 int nfft3_set_stream(nfft3_plan_t p, void *stream);
@@ -193,7 +213,10 @@ int nfft3_batch_trafo_noalloc(int T, const nfft3_plan_t *plans, const void *cons
 
 /* psi_dev[j] = psi(xi_j) for the M points xi_dev ((M, 3) FP64, physical
  * coordinates; any finite values, the series being periodic on Omega) and
- * coefficients psihat_dev (plan dtype); a_d < b_d (host arrays).  Sets the
+ * coefficients psihat_dev (plan dtype); a_d < b_d (host arrays).  On a plan
+ * of d < 3 axes (nfft3_plan_nd) a and b hold d entries and xi_dev is (M, d):
+ * the one- and two-dimensional series of the paper's infft / infft2
+ * (Appendix B).  Sets the
  * plan's points to the mapped xi (as nfft3_set_points, including its
  * synchronisation and NFFT3_ERR_NONFINITE) and leaves them set; the mapped
  * points and coefficients live in plan-owned scratch (allocated on first
@@ -260,7 +283,11 @@ typedef struct nfft3_rgrid_s *nfft3_rgrid_t;
 
 /* Plan for N[3] coefficients (N_d even, 2 <= N_d <= 16384) and M[3] grid
  * points per axis (1 <= M_d <= 2^20), dtype NFFT3_C64 / NFFT3_C128, on the
- * current device and the given stream (NULL = default).  Allocates the E^d
+ * current device and the given stream (NULL = default).  Leading unit axes,
+ * N_0 = M_0 = 1 (or also N_1 = M_1 = 1), give the two-dimensional form (the
+ * double matrix product of the paper's igridft2, Appendix B) and the
+ * one-dimensional one (the matrix-vector product E psihat of Appendix B):
+ * their products are skipped and their coordinate pointers may be NULL.  Allocates the E^d
  * tables and two intermediates of N0 N1 M2 and N0 M1 M2 complex values. */
 int nfft3_rgrid_plan(nfft3_rgrid_t *out, const int64_t N[3], const int64_t M[3], int dtype, void *stream);
 int nfft3_rgrid_set_stream(nfft3_rgrid_t g, void *stream);

@@ -1,4 +1,4 @@
-"""MI355X (gfx950) nonequispaced FFT in three dimensions.
+"""MI355X (gfx950) nonequispaced FFT in one, two and three dimensions.
 
 Python binding of ``libnfft3.so`` (C ABI in ``include/nfft3.h``).  This
 module only marshals arguments: every step of the computation -- point
@@ -20,13 +20,15 @@ periodically).
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Sequence
 
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 from ._lib import NFFT3_C64, NFFT3_C128, NFFT3Error, check, lib
 
-__all__ = ["Plan", "RectGrid", "GPE", "type2", "batch_trafo", "deconv_factors", "window_poly", "NFFT3Error"]
+__all__ = ["Plan", "RectGrid", "GPE", "type2", "batch_trafo", "infft", "infft2", "infft3", "deconv_factors",
+           "window_poly", "NFFT3Error"]
 
 _DT = {torch.complex64: NFFT3_C64, torch.complex128: NFFT3_C128}
 
@@ -36,8 +38,10 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
 
 
 class Plan:
-    """A 3-D NFFT plan: coefficient sizes N, oversampling sigma, window
-    half-width m, precision dtype (torch.complex64 or torch.complex128)."""
+    """An NFFT plan: coefficient sizes N (1, 2 or 3 axes: the one-, two- and
+    three-dimensional series), oversampling sigma, window half-width m,
+    precision dtype (torch.complex64 or torch.complex128).  Points are
+    (M, len(N)) float64 arrays."""
 
     def __init__(self, N: Sequence[int], sigma: float = 2.0, m: int = 8,
                  dtype: torch.dtype = torch.complex128, device=None):
@@ -47,18 +51,21 @@ class Plan:
         if self.device.type != "cuda":
             raise ValueError("Plan needs a GPU device")
         self.N = tuple(int(v) for v in N)
+        self.dim = len(self.N)
+        if self.dim not in (1, 2, 3):
+            raise ValueError("N must have 1, 2 or 3 entries")
         self.sigma = float(sigma)
         self.m = int(m)
         self.dtype = dtype
         self._h = ctypes.c_void_p()
-        Narr = (ctypes.c_int64 * 3)(*self.N)
+        Narr = (ctypes.c_int64 * self.dim)(*self.N)
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            check(lib.nfft3_plan(ctypes.byref(self._h), Narr, self.sigma, self.m, _DT[dtype],
-                                 ctypes.c_void_p(stream)), "nfft3_plan")
+            check(lib.nfft3_plan_nd(ctypes.byref(self._h), self.dim, Narr, self.sigma, self.m, _DT[dtype],
+                                    ctypes.c_void_p(stream)), "nfft3_plan_nd")
         n = (ctypes.c_int64 * 3)()
         check(lib.nfft3_get_info(self._h, n, None), "nfft3_get_info")
-        self.n = tuple(int(v) for v in n)
+        self.n = tuple(int(v) for v in n)[3 - self.dim:]
         self.M = 0
         self.epoch = 0
 
@@ -88,6 +95,13 @@ class Plan:
             raise ValueError("out must be a contiguous tensor")
         return out
 
+    def _points(self, x: torch.Tensor) -> torch.Tensor:
+        if x.dim() != 2 or x.shape[1] != self.dim:
+            raise ValueError(f"points must have shape (M, {self.dim})")
+        if x.dtype != torch.float64 or x.device != self.device:
+            raise TypeError("points must be float64 on the plan's device")
+        return x.contiguous()
+
     def close(self):
         if self._h:
             lib.nfft3_destroy(self._h)
@@ -101,12 +115,8 @@ class Plan:
 
     # -- the C ABI ---------------------------------------------------------
     def set_points(self, x: torch.Tensor) -> None:
-        """x: (M, 3) float64 on the plan's device."""
-        if x.dim() != 2 or x.shape[1] != 3:
-            raise ValueError("points must have shape (M, 3)")
-        if x.dtype != torch.float64 or x.device != self.device:
-            raise TypeError("points must be float64 on the plan's device")
-        x = x.contiguous()
+        """x: (M, dim) float64 on the plan's device."""
+        x = self._points(x)
         self._bind_stream()
         self.epoch += 1
         self.M = 0
@@ -118,12 +128,9 @@ class Plan:
         x (nfft3_points_unchanged compares every folded coordinate on the
         device, so writes that bypass the tensor's version counter, such as
         through .data, are seen).  Returns True if the points were sorted."""
-        if x.dim() != 2 or x.shape[1] != 3:
-            raise ValueError("points must have shape (M, 3)")
-        if x.dtype != torch.float64 or x.device != self.device:
-            raise TypeError("points must be float64 on the plan's device")
+        x = self._points(x)
         if self.M == x.shape[0]:
-            xc = x.contiguous()
+            xc = x
             same = ctypes.c_int(0)
             self._bind_stream()
             check(lib.nfft3_points_unchanged(self._h, xc.shape[0], _ptr(xc), ctypes.byref(same)),
@@ -142,9 +149,12 @@ class Plan:
         check(lib.nfft3_trafo(self._h, _ptr(fhat), _ptr(out)), "nfft3_trafo")
         return out
 
-    def trafo_fields(self, fhat: torch.Tensor, deriv_mask: int = 7) -> torch.Tensor:
-        """(1 + popcount(mask), M): the field and its derivative fields."""
+    def trafo_fields(self, fhat: torch.Tensor, deriv_mask: int | None = None) -> torch.Tensor:
+        """(1 + popcount(mask), M): the field and its derivative fields (bit
+        d of the mask = the plan's axis d; default all axes)."""
         fhat = self._coeffs(fhat)
+        if deriv_mask is None:
+            deriv_mask = (1 << self.dim) - 1
         k = 1 + bin(deriv_mask & 7).count("1")
         out = torch.empty((k, self.M), dtype=self.dtype, device=self.device)
         self._bind_stream()
@@ -161,29 +171,28 @@ class Plan:
         return out
 
     def grad_points(self, fhat: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
-        """(M, 3) float64: Re(conj(G_j) d f_j / d x_{j,d})."""
+        """(M, dim) float64: Re(conj(G_j) d f_j / d x_{j,d})."""
         fhat = self._coeffs(fhat)
         G = self._values(G)
-        out = torch.empty((self.M, 3), dtype=torch.float64, device=self.device)
+        out = torch.empty((self.M, self.dim), dtype=torch.float64, device=self.device)
         self._bind_stream()
         check(lib.nfft3_grad_points(self._h, _ptr(fhat), _ptr(G), _ptr(out)), "nfft3_grad_points")
         return out
 
     # -- the series on a physical domain (eq. (fs)) and vortex tubes ---------
-    @staticmethod
-    def _domain(a, b):
-        a = (ctypes.c_double * 3)(*[float(v) for v in a])
-        b = (ctypes.c_double * 3)(*[float(v) for v in b])
-        return a, b
+    def _domain(self, a, b):
+        a, b = [float(v) for v in a], [float(v) for v in b]
+        if len(a) != self.dim or len(b) != self.dim:
+            raise ValueError(f"a and b must have {self.dim} entries")
+        return (ctypes.c_double * self.dim)(*a), (ctypes.c_double * self.dim)(*b)
 
     def infft3(self, psihat: torch.Tensor, a, b, xi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """psi(xi) = sum_k psihat_k prod_d exp(2 pi i k_d (xi_d - a_d)/(b_d - a_d)) / sqrt(b_d - a_d)
-        at the (M, 3) float64 points xi of the domain prod [a_d, b_d); the
-        plan's points become the mapped xi."""
+        at the (M, dim) float64 points xi of the domain prod [a_d, b_d) (for
+        dim 1 and 2 the paper's infft and infft2); the plan's points become
+        the mapped xi."""
         psihat = self._coeffs(psihat)
-        if xi.dim() != 2 or xi.shape[1] != 3 or xi.dtype != torch.float64 or xi.device != self.device:
-            raise TypeError("points must be (M, 3) float64 on the plan's device")
-        xi = xi.contiguous()
+        xi = self._points(xi)
         M = int(xi.shape[0])
         if out is None:
             out = torch.empty(M, dtype=self.dtype, device=self.device)
@@ -198,6 +207,8 @@ class Plan:
         self.M = M
         return out
 
+    infft = infft3      # any number of axes: the paper's infft / infft2 / infft3
+
     def tube_refine(self, psihat: torch.Tensor, a, b, rhobar: Sequence[float], cap: int | None = None):
         """Evaluation within vortex tubes (Sec. 4.3): returns (points (K, 3)
         float64, rho (K,) float64) of the last refined set."""
@@ -208,7 +219,7 @@ class Plan:
         count = ctypes.c_int64(0)
         self._bind_stream()
         if cap is None:
-            n = self.N[0] * self.N[1] * self.N[2]
+            n = math.prod(self.N)
             cap = n if L == 0 else 0        # first pass sizes the output
         pts = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=self.device)
         rho = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device)
@@ -246,9 +257,7 @@ class Plan:
     def autotune(self, x: torch.Tensor, fhat: torch.Tensor, reps: int = 3):
         """Time trafo for every binning candidate on these points and
         coefficients, keep the fastest (points stay set).  Returns (tile, items)."""
-        if x.dim() != 2 or x.shape[1] != 3 or x.dtype != torch.float64 or x.device != self.device:
-            raise TypeError("points must be (M, 3) float64 on the plan's device")
-        x = x.contiguous()
+        x = self._points(x)
         fhat = self._coeffs(fhat)
         out = torch.empty(x.shape[0], dtype=self.dtype, device=self.device)
         t, i = ctypes.c_int(), ctypes.c_int()
@@ -360,7 +369,9 @@ class RectGrid:
     """The series at a rectilinear grid y0 x y1 x y2 (Sec. 2.1), exact up to
     rounding: F[i0, i1, i2] = sum_k fhat_k exp(-2 pi i (k0 y0[i0] + k1 y1[i1]
     + k2 y2[i2])), computed as three complex matrix products on the matrix
-    cores.  N: coefficient sizes; M: grid points per axis."""
+    cores.  N: coefficient sizes; M: grid points per axis (1, 2 or 3 axes:
+    with two, the double matrix product of the paper's igridft2; with one,
+    the matrix-vector product E psihat)."""
 
     def __init__(self, N: Sequence[int], M: Sequence[int], dtype: torch.dtype = torch.complex128, device=None):
         if dtype not in _DT:
@@ -370,12 +381,16 @@ class RectGrid:
             raise ValueError("RectGrid needs a GPU device")
         self.N = tuple(int(v) for v in N)
         self.M = tuple(int(v) for v in M)
+        self.dim = len(self.N)
+        if self.dim not in (1, 2, 3) or len(self.M) != self.dim:
+            raise ValueError("N and M must have the same length, 1, 2 or 3")
         self.dtype = dtype
         self._h = ctypes.c_void_p()
+        pad = (1,) * (3 - self.dim)      # leading unit axes
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            check(lib.nfft3_rgrid_plan(ctypes.byref(self._h), (ctypes.c_int64 * 3)(*self.N),
-                                       (ctypes.c_int64 * 3)(*self.M), _DT[dtype], ctypes.c_void_p(stream)),
+            check(lib.nfft3_rgrid_plan(ctypes.byref(self._h), (ctypes.c_int64 * 3)(*(pad + self.N)),
+                                       (ctypes.c_int64 * 3)(*(pad + self.M)), _DT[dtype], ctypes.c_void_p(stream)),
                   "nfft3_rgrid_plan")
         self._axes = None
 
@@ -383,15 +398,19 @@ class RectGrid:
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib.nfft3_rgrid_set_stream(self._h, ctypes.c_void_p(s)), "nfft3_rgrid_set_stream")
 
-    def set_axes(self, y0: torch.Tensor, y1: torch.Tensor, y2: torch.Tensor) -> None:
-        """Grid coordinates per axis: float64 vectors of M_d values on the device."""
-        ys = []
-        for d, y in enumerate((y0, y1, y2)):
+    def set_axes(self, *ys: torch.Tensor) -> None:
+        """Grid coordinates per axis: one float64 vector of M_d values on the
+        device per axis."""
+        if len(ys) != self.dim:
+            raise ValueError(f"expected {self.dim} coordinate vectors")
+        ys = list(ys)
+        for d, y in enumerate(ys):
             if y.dtype != torch.float64 or y.device != self.device or y.numel() != self.M[d]:
                 raise ValueError(f"y{d} must be {self.M[d]} float64 values on {self.device}")
-            ys.append(y.contiguous())
+            ys[d] = y.contiguous()
+        ptrs = [ctypes.c_void_p()] * (3 - self.dim) + [_ptr(y) for y in ys]   # unit axes: NULL
         self._bind_stream()
-        check(lib.nfft3_rgrid_set_axes(self._h, *[_ptr(y) for y in ys]), "nfft3_rgrid_set_axes")
+        check(lib.nfft3_rgrid_set_axes(self._h, *ptrs), "nfft3_rgrid_set_axes")
         self._axes = ys
 
     def eval(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -480,6 +499,35 @@ class _Type2(torch.autograd.Function):
         gf = plan.adjoint(G) if ctx.needs_input_grad[0] else None
         gx = plan.grad_points(fhat.detach(), G) if ctx.needs_input_grad[1] else None
         return gf, gx, None
+
+
+def _infft_call(psihat: torch.Tensor, a, b, xi: torch.Tensor, dim: int, m: int, sigma: float) -> torch.Tensor:
+    if psihat.dim() != dim:
+        raise ValueError(f"coefficients must have {dim} axes")
+    plan = Plan(tuple(psihat.shape), sigma=sigma, m=m, dtype=psihat.dtype, device=psihat.device)
+    try:
+        return plan.infft3(psihat, a, b, xi.reshape(-1, dim))
+    finally:
+        plan.close()
+
+
+def infft(psihat: torch.Tensor, a: float, b: float, xi: torch.Tensor, m: int = 8, sigma: float = 2.0):
+    """The one-dimensional series on [a, b) at the points xi (Appendix B's
+    infft): psi(xi) = sum_k psihat_k exp(2 pi i k (xi - a)/(b - a)) / sqrt(b - a),
+    k = -N/2 .. N/2-1.  Makes a plan for the call."""
+    return _infft_call(psihat, [a], [b], xi, 1, m, sigma)
+
+
+def infft2(psihat: torch.Tensor, a, b, xi: torch.Tensor, m: int = 8, sigma: float = 2.0):
+    """The two-dimensional series on [a0, b0) x [a1, b1) at the (M, 2)
+    points xi (Appendix B's infft2).  Makes a plan for the call."""
+    return _infft_call(psihat, a, b, xi, 2, m, sigma)
+
+
+def infft3(psihat: torch.Tensor, a, b, xi: torch.Tensor, m: int = 8, sigma: float = 2.0):
+    """The three-dimensional series of eq. (fs) at the (M, 3) points xi.
+    Makes a plan for the call (Plan.infft3 reuses one)."""
+    return _infft_call(psihat, a, b, xi, 3, m, sigma)
 
 
 def type2(fhat: torch.Tensor, x: torch.Tensor, plan: Plan) -> torch.Tensor:

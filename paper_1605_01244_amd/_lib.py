@@ -49,6 +49,7 @@ def _load() -> ctypes.CDLL:
     ci = ctypes.c_int
     sig = {
         "nfft3_plan": ([ctypes.POINTER(vp), i64p, ctypes.c_double, ci, ci, vp], ci),
+        "nfft3_plan_nd": ([ctypes.POINTER(vp), ci, i64p, ctypes.c_double, ci, ci, vp], ci),
         "nfft3_set_stream": ([vp, vp], ci),
         "nfft3_set_points": ([vp, i64, vp], ci),
         "nfft3_points_unchanged": ([vp, i64, vp, ctypes.POINTER(ci)], ci),

@@ -153,8 +153,10 @@ static void free_points(nfft3_plan_impl *p) {
     (void)hipFree(p->tz); p->tz = nullptr;
     (void)hipFree(p->chunk_base); p->chunk_base = nullptr;
     (void)hipFree(p->sort_scratch); p->sort_scratch = nullptr;
+    (void)hipFree(p->xin); p->xin = nullptr;
     p->chunk_base_cap = 0;
     p->cap_pts = 0;
+    p->cap_xin = 0;
 }
 
 static void free_bins(nfft3_plan_impl *p) {
@@ -185,6 +187,11 @@ static int validate(const int64_t N[3], double sigma, int m, int dtype, int64_t 
     if (!(sigma > 1.0) || !isfinite(sigma)) return NFFT3_ERR_INVALID_ARG;
     if (m < 1 || m > 10) return NFFT3_ERR_INVALID_ARG;
     for (int d = 0; d < 3; ++d) {
+        // leading unit axes (N_0 = 1, or N_0 = N_1 = 1): lower-dimensional plans
+        if (N[d] == 1 && d < 2 && (d == 0 || N[0] == 1)) {
+            n[d] = 1;
+            continue;
+        }
         if (N[d] < 2 || (N[d] % 2) != 0 || N[d] > 4096) return NFFT3_ERR_INVALID_ARG;
         double nd = sigma * (double)N[d];
         int64_t ni = (int64_t)llround(nd);
@@ -298,8 +305,8 @@ static int build_plan(nfft3_plan_impl *p) {
     NFFT3_HIP_TRY(hipMalloc(&p->grid, total * p->elt));
     NFFT3_HIP_TRY(hipMalloc(&p->flag, 64));
     for (int d = 0; d < 3; ++d) {
-        std::vector<double> c((size_t)p->N[d]);
-        deconv_factors(p->N[d], p->n[d], p->m, p->b, c.data());
+        std::vector<double> c((size_t)p->N[d], 1.0);      // unit axis: exact, factor 1
+        if (!(p->unit >> d & 1)) deconv_factors(p->N[d], p->n[d], p->m, p->b, c.data());
         int rc = f64 ? upload_real<double>(c, &p->cdec[d]) : upload_real<float>(c, &p->cdec[d]);
         if (rc) return rc;
         std::vector<int> rad;
@@ -351,7 +358,11 @@ int nfft3_plan(nfft3_plan_t *out, const int64_t N[3], double sigma, int m, int d
     p->m = m;
     p->sigma = sigma;
     p->b = M_PI * (2.0 - 1.0 / sigma);
-    for (int d = 0; d < 3; ++d) { p->N[d] = N[d]; p->n[d] = n[d]; }
+    for (int d = 0; d < 3; ++d) {
+        p->N[d] = N[d];
+        p->n[d] = n[d];
+        if (N[d] == 1) p->unit |= 1 << d;
+    }
     p->stream = (hipStream_t)stream;
     p->elt = dtype == NFFT3_C128 ? 16 : 8;
     rc = build_plan(p);
@@ -362,6 +373,21 @@ int nfft3_plan(nfft3_plan_t *out, const int64_t N[3], double sigma, int m, int d
     }
     *out = p;
     return NFFT3_OK;
+}
+
+int nfft3_plan_nd(nfft3_plan_t *out, int d, const int64_t *N, double sigma, int m, int dtype, void *stream) {
+    if (!out) return NFFT3_ERR_NULL;
+    *out = nullptr;
+    if (!N) return NFFT3_ERR_NULL;
+    if (d < 1 || d > 3) return NFFT3_ERR_INVALID_ARG;
+    int64_t N3[3] = {1, 1, 1};
+    for (int i = 0; i < d; ++i) {
+        if (N[i] < 2) return NFFT3_ERR_INVALID_ARG;     // unit axes are the padding only
+        N3[3 - d + i] = N[i];
+    }
+    int rc = nfft3_plan(out, N3, sigma, m, dtype, stream);
+    if (rc == NFFT3_OK) (*out)->dim = d;
+    return rc;
 }
 
 int nfft3_set_stream(nfft3_plan_t p, void *stream) {
@@ -375,6 +401,30 @@ int nfft3_destroy(nfft3_plan_t p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     free_plan(p);
     delete p;
+    return NFFT3_OK;
+}
+
+// Points of a plan with dim < 3 coordinates: widened on the device to the
+// (M, 3) layout of the kernels (0 on the unit axes) in the plan's xin.
+static int widen(nfft3_plan_impl *p, int64_t M, const double **x) {
+    if (p->dim == 3 || M == 0) return NFFT3_OK;
+    if (M > p->cap_xin) {
+        (void)hipFree(p->xin);
+        p->xin = nullptr;
+        p->cap_xin = 0;
+        NFFT3_HIP_TRY(hipMalloc(&p->xin, sizeof(double) * 3 * M));
+        p->cap_xin = M;
+    }
+    int rc = launch_widen_points(p->stream, M, p->dim, *x, p->xin);
+    if (rc) return rc;
+    *x = p->xin;
+    return NFFT3_OK;
+}
+
+// a derivative mask over the plan's own axes -> over the three kernel axes
+static int kernel_mask(const nfft3_plan_impl *p, int mask, int *out) {
+    if (mask < 0 || mask >= (1 << p->dim)) return NFFT3_ERR_INVALID_ARG;
+    *out = mask << (3 - p->dim);
     return NFFT3_OK;
 }
 
@@ -406,8 +456,10 @@ int nfft3_set_points(nfft3_plan_t p, int64_t M, const double *x) {
         NFFT3_HIP_TRY(hipMalloc(&p->sort_scratch, sizeof(int) * (size_t)(bases / 1024 + 2)));
         p->chunk_base_cap = bases;
     }
+    int rc = widen(p, M, &x);
+    if (rc) return rc;
     int flag = 0;
-    int rc = launch_set_points(p, M, x, &flag);
+    rc = launch_set_points(p, M, x, &flag);
     if (rc) return rc;
     if (flag & 1) return NFFT3_ERR_NONFINITE;
     p->M = M;
@@ -422,6 +474,8 @@ int nfft3_points_unchanged(nfft3_plan_t p, int64_t M, const double *x, int *unch
     if (M < 0) return NFFT3_ERR_INVALID_ARG;
     if (!p->have_points || M != p->M) return NFFT3_OK;
     if (M > 0 && !x) return NFFT3_ERR_NULL;
+    int rc = widen(p, M, &x);
+    if (rc) return rc;
     return launch_points_equal(p, M, x, unchanged);
 }
 
@@ -437,7 +491,8 @@ int nfft3_trafo(nfft3_plan_t p, const void *fhat, void *f) {
 int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat, void *out, int mask) {
     if (!p) return NFFT3_ERR_NULL;
     if (!p->have_points) return NFFT3_ERR_NO_POINTS;
-    if (mask < 0 || mask > 7) return NFFT3_ERR_INVALID_ARG;
+    int rc0 = kernel_mask(p, mask, &mask);
+    if (rc0) return rc0;
     if (!fhat || (p->M > 0 && !out)) return NFFT3_ERR_NULL;
     if (p->dtype == NFFT3_C128 && mask != 0) {
         // FP64: the derivative fields through the window derivative, from
@@ -495,6 +550,7 @@ static int batch_common(int T, const nfft3_plan_t *plans, const void *const *fha
         if (plans[t]->m != plans[0]->m || plans[t]->sigma != plans[0]->sigma || plans[t]->m > 8)
             return NFFT3_ERR_INVALID_ARG;
         if (plans[t]->device != plans[0]->device) return NFFT3_ERR_INVALID_ARG;
+        if (plans[t]->unit) return NFFT3_ERR_INVALID_ARG;     // three-dimensional plans only
         for (int u = 0; u < t; ++u)
             if (plans[u] == plans[t]) return NFFT3_ERR_INVALID_ARG;
     }
@@ -653,8 +709,14 @@ int nfft3_infft3(nfft3_plan_t p, const double a[3], const double b[3], const voi
     if (!p || !a || !b || !psihat) return NFFT3_ERR_NULL;
     if (M < 0 || M > (int64_t)INT32_MAX / 3) return NFFT3_ERR_INVALID_ARG;
     if (M > 0 && (!xi || !psi)) return NFFT3_ERR_NULL;
-    if (!domain_ok(a, b)) return NFFT3_ERR_INVALID_ARG;
-    return launch_infft3(p, a, b, psihat, M, xi, psi);
+    // a, b hold one entry per plan axis; unit axes take [0, 1)
+    double a3[3] = {0.0, 0.0, 0.0}, b3[3] = {1.0, 1.0, 1.0};
+    for (int i = 0; i < p->dim; ++i) {
+        a3[3 - p->dim + i] = a[i];
+        b3[3 - p->dim + i] = b[i];
+    }
+    if (!domain_ok(a3, b3)) return NFFT3_ERR_INVALID_ARG;
+    return launch_infft3(p, a3, b3, psihat, M, xi, psi);
 }
 
 int nfft3_tube_refine(nfft3_plan_t p, const double a[3], const double b[3], const void *psihat, int levels,
@@ -665,6 +727,7 @@ int nfft3_tube_refine(nfft3_plan_t p, const double a[3], const double b[3], cons
     if (levels > 0 && !rhobar) return NFFT3_ERR_NULL;
     if (cap > 0 && (!pts || !rho)) return NFFT3_ERR_NULL;
     if (!domain_ok(a, b)) return NFFT3_ERR_INVALID_ARG;
+    if (p->unit || p->dim != 3) return NFFT3_ERR_INVALID_ARG;     // the refinement grids are three-dimensional
     if (p->N[0] * p->N[1] * p->N[2] > (int64_t)INT32_MAX / 3) return NFFT3_ERR_INVALID_ARG;
     return launch_tube_refine(p, a, b, psihat, levels, rhobar, cap, pts, rho, count);
 }
@@ -684,6 +747,8 @@ int nfft3_rgrid_plan(nfft3_rgrid_t *out, const int64_t N[3], const int64_t M[3],
     if (!N || !M) return NFFT3_ERR_NULL;
     if (dtype != NFFT3_C64 && dtype != NFFT3_C128) return NFFT3_ERR_DTYPE;
     for (int d = 0; d < 3; ++d) {
+        // leading unit axes (N_d = M_d = 1): the two- and one-dimensional forms
+        if (N[d] == 1 && M[d] == 1 && d < 2 && (d == 0 || N[0] == 1)) continue;
         if (N[d] < 2 || N[d] % 2 || N[d] > kRgridMaxN) return NFFT3_ERR_INVALID_ARG;
         if (M[d] < 1 || M[d] > kRgridMaxM) return NFFT3_ERR_INVALID_ARG;
     }
@@ -722,7 +787,9 @@ int nfft3_rgrid_set_stream(nfft3_rgrid_t g, void *stream) {
 
 int nfft3_rgrid_set_axes(nfft3_rgrid_t g, const double *y0, const double *y1, const double *y2) {
     if (!g) return NFFT3_ERR_NULL;
-    if (!y0 || !y1 || !y2) return NFFT3_ERR_NULL;
+    // a unit axis reads no coordinate (its pointer may be NULL)
+    if ((!y0 && !(g->N[0] == 1 && g->M[0] == 1)) || (!y1 && !(g->N[1] == 1 && g->M[1] == 1)) || !y2)
+        return NFFT3_ERR_NULL;
     g->have_axes = false;
     const double *y[3] = {y0, y1, y2};
     int rc = launch_rgrid_axes(g, y);

@@ -12,6 +12,7 @@
 //   pass 2 (axis 1): grid[i0][0..N1)[x] -> grid[i0][0..n1)[x]  i0<N0
 //   pass 3 (axis 0): grid[0..N0)[y][x] -> grid[0..n0)[y][x]
 // and the adjoint keeps only the N_d outputs per line in reverse order.
+// Leading unit axes (lower-dimensional plans, n_d = N_d = 1) have no pass.
 // Compact index i of a pruned line holds frequency i - L/2, which sits at
 // FFT position (i - L/2) mod n.
 #include "fft_dev.h"
@@ -126,18 +127,21 @@ template <typename T>
 static int grid_forward(nfft3_plan_impl *p, const void *fhat, int deriv) {
     int rc = rows_pass<T>(p, 0, fhat, p->grid, deriv);
     if (rc) return rc;
+    // (a unit axis, n = N = 1, has no pass: its transform is the identity)
     // axis 1: tiles over i0 < N0 (outer stride n1 n2)
-    rc = cols_pass<T>(p, 1, true, (int)p->N[1], (int)p->n[1], p->N[0], p->n[1] * p->n[2]);
+    if (p->n[1] > 1) rc = cols_pass<T>(p, 1, true, (int)p->N[1], (int)p->n[1], p->N[0], p->n[1] * p->n[2]);
     if (rc) return rc;
     // axis 0: tiles over y < n1 (outer stride n2)
-    return cols_pass<T>(p, 0, true, (int)p->N[0], (int)p->n[0], p->n[1], p->n[2]);
+    if (p->n[0] > 1) rc = cols_pass<T>(p, 0, true, (int)p->N[0], (int)p->n[0], p->n[1], p->n[2]);
+    return rc;
 }
 
 template <typename T>
 static int grid_adjoint(nfft3_plan_impl *p, void *fhat) {
-    int rc = cols_pass<T>(p, 0, false, (int)p->n[0], (int)p->N[0], p->n[1], p->n[2]);
+    int rc = NFFT3_OK;
+    if (p->n[0] > 1) rc = cols_pass<T>(p, 0, false, (int)p->n[0], (int)p->N[0], p->n[1], p->n[2]);
     if (rc) return rc;
-    rc = cols_pass<T>(p, 1, false, (int)p->n[1], (int)p->N[1], p->N[0], p->n[1] * p->n[2]);
+    if (p->n[1] > 1) rc = cols_pass<T>(p, 1, false, (int)p->n[1], (int)p->N[1], p->N[0], p->n[1] * p->n[2]);
     if (rc) return rc;
     return rows_pass<T>(p, 1, p->grid, fhat, -1);
 }

@@ -6,7 +6,9 @@
 // (Euclidean remainder) with fhat_k = psihat_k (-1)^(k_0 + k_1 + k_2) /
 // prod sqrt(b_d - a_d): with t = (xi - a)/(b - a), zeta = 1/2 - t mod 1 and
 // exp(-2 pi i k zeta) = (-1)^k exp(2 pi i k t), whose sign the coefficient
-// factor cancels.  Here k_d = i_d - N_d/2 for array index i_d.
+// factor cancels.  Here k_d = i_d - N_d/2 for array index i_d.  A plan of
+// fewer axes (the one- and two-dimensional series) takes a_d = 0, b_d = 1 on
+// its unit axes, where k_d = 0 and both factors are 1.
 //
 // Tube refinement: start from the points of the regular grid X_N of the
 // domain (x_{d,n} = a_d + n h_d) and rho = |psi|^2 there; for each threshold
@@ -32,11 +34,12 @@ __device__ __forceinline__ double euclid_mod1(double v) {
 }
 
 // zeta = mod((xi - a)/(a - b), 1) - 1/2; NaN / Inf pass through (set_points
-// reports them)
-__global__ void map_points_kernel(const double *__restrict__ xi, int64_t M, Domain D, double *__restrict__ zeta) {
+// reports them).  Points of dim coordinates: the plan's last dim axes.
+__global__ void map_points_kernel(const double *__restrict__ xi, int64_t M, int dim, Domain D,
+                                  double *__restrict__ zeta) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 3 * M) return;
-    const int d = (int)(e % 3);
+    if (e >= dim * M) return;
+    const int d = 3 - dim + (int)(e % dim);
     const double v = xi[e];
     zeta[e] = isfinite(v) ? euclid_mod1((v - D.a[d]) * D.inv[d]) - 0.5 : v;
 }
@@ -120,14 +123,14 @@ int launch_infft3(nfft3_plan_impl *p, const double a[3], const double b[3], cons
     const Domain D = make_domain(p, a, b);
     hipStream_t s = p->stream;
     InfftmScratch &S = p->infftm;
-    int rc = ensure(&S.zeta, &S.zeta_cap, 3 * M, sizeof(double));
+    int rc = ensure(&S.zeta, &S.zeta_cap, p->dim * M, sizeof(double));
     if (rc) return rc;
     const int64_t nc = p->N[0] * p->N[1] * p->N[2];
     rc = ensure(&S.fhat, &S.fhat_cap, nc, p->elt);
     if (rc) return rc;
     if (M > 0) {
-        hipLaunchKernelGGL(map_points_kernel, dim3((unsigned)((3 * M + 255) / 256)), dim3(256), 0, s, xi, M, D,
-                           (double *)S.zeta);
+        hipLaunchKernelGGL(map_points_kernel, dim3((unsigned)((p->dim * M + 255) / 256)), dim3(256), 0, s, xi, M,
+                           p->dim, D, (double *)S.zeta);
         NFFT3_LAUNCH_CHECK("map_points_kernel");
     }
     double scale = 1.0;

@@ -168,6 +168,14 @@ struct nfft3_plan_impl {
     hipStream_t stream = nullptr;
     int device = 0;
     size_t elt = 16;          // bytes per complex element
+    // Lower-dimensional transforms: a plan of d < 3 axes is the 3-D plan with
+    // 3 - d leading unit axes (N = n = 1: frequency 0 only, so the sum over
+    // such an axis is exact and needs no window).  dim = coordinates per
+    // caller point; unit bit d = axis d is a unit axis.
+    int dim = 3;
+    int unit = 0;
+    double *xin = nullptr;    // dim < 3: caller points widened to (M,3)
+    int64_t cap_xin = 0;
 
     void *grid = nullptr;     // n0 n1 n2 complex
     std::vector<void *> extra_grids;   // batched derivative fields
@@ -264,6 +272,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x, int *flag)
 // chunk bases the two-level sort needs for M points, -1 if it is not used
 int64_t two_level_bases(const nfft3_plan_impl *p, int64_t M);
 // *equal = 1 when the sorted points are those of x (no new sort needed)
+int launch_widen_points(hipStream_t s, int64_t M, int dim, const double *x, double *x3);
 int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equal);
 // window sums and their point derivative (interp.hip)
 int launch_interp(nfft3_plan_impl *p, const void *grid, void *f);

@@ -123,6 +123,8 @@ struct PSArgs {
     int qinv;               // interp: inverse of (row stride in 16-B units / D) mod 16/D
     int fmask;              // fields: derivative axes written after the field (bit d = axis d)
     int64_t fstride;        // fields: elements between consecutive output blocks (M)
+    int unit;               // bit 0: axis 0 is a unit axis (one plane, weight 1); bit 1: axis 1 too
+    int gdim;               // grad: components per point written (the last gdim axes)
 };
 
 // What the window-sum body computes at each point.
@@ -163,6 +165,10 @@ __device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int
     const int zmax = cell_frac<float>(a.xs[3 * ((int64_t)hi - 1)], a.n0, dummy);
     it.zbeg = zmin - m + 1;
     it.nplanes = zmax - zmin + 2 * m;
+    if (a.unit & 1) {       // unit axis 0: the one plane, weight 1
+        it.zbeg = 0;
+        it.nplanes = 1;
+    }
     it.PY = a.By + 2 * m - 1;
     it.PX = a.Bx + 2 * m - 1;
     it.psz = it.PY * it.PX;
@@ -400,13 +406,19 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
             const int yc = cell_frac<T>(xp[1], a.n1, f1);
             const int xc = cell_frac<T>(xp[2], a.n2, f2);
             s = (yc - it.y0) * it.PXp + (xc - it.x0);
-            zlo[k] = zc - m + 1 - it.zbeg;      // first plane index of the stencil
+            zlo[k] = (a.unit & 1) ? 0 : zc - m + 1 - it.zbeg;      // first plane index of the stencil
             if constexpr (GRAD) {
                 window_weights_d<T, W>(f1, coef, a.deg, w1[k], d1[k]);
                 window_weights_d<T, W>(f2, coef, a.deg, w2, e2);
             } else {
                 window_weights<T, W>(f1, coef, a.deg, w1[k]);
                 window_weights<T, W>(f2, coef, a.deg, w2);
+            }
+            if (a.unit & 2) {   // unit axis 1: every region row is grid row 0; weight 1 on one
+#pragma unroll
+                for (int r = 0; r < W; ++r) w1[k][r] = r == 0 ? (T)1 : (T)0;
+#pragma unroll
+                for (int r = 0; r < WG; ++r) d1[k][r] = 0;
             }
         }
         // first unit of the stencil row: complex<double> at s; complex<float>
@@ -485,7 +497,8 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
             if (r0 >= 0 && r0 < W) {
                 T dw0 = 0;
                 T w0;
-                if constexpr (GRAD) w0 = piece_d<T>(scoef + r0 * zrow, a.deg, f0[k], dw0);
+                if (a.unit & 1) w0 = 1;
+                else if constexpr (GRAD) w0 = piece_d<T>(scoef + r0 * zrow, a.deg, f0[k], dw0);
                 else if (zfix) w0 = piece_fixed<T, ZC>(scoef + r0 * ZC, f0[k]);
                 else w0 = piece<T>(scoef + r0 * zrow, a.deg, f0[k]);
                 T sr = 0, si = 0;
@@ -603,10 +616,12 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
         } else if constexpr (GRAD) {
             // Re(conj(G) D) = G.x D.x + G.y D.y, times n_d (dt/dx)
             const c_t<T> g = ((const c_t<T> *)a.vals)[pj];
-            double *gx = (double *)a.out + 3 * (int64_t)pj;
-            gx[0] = (double)a.n0 * ((double)g.x * (double)ar[k] + (double)g.y * (double)ai[k]);
-            gx[1] = (double)a.n1 * ((double)g.x * (double)g1r[k] + (double)g.y * (double)g1i[k]);
-            gx[2] = (double)a.n2 * ((double)g.x * (double)g2r[k] + (double)g.y * (double)g2i[k]);
+            // the last gdim components (a plan of fewer axes drops its unit axes)
+            double *gx = (double *)a.out + (int64_t)a.gdim * pj;
+            const int c0 = 3 - a.gdim;     // component of axis d is gx[d - c0]
+            if (c0 == 0) gx[0] = (double)a.n0 * ((double)g.x * (double)ar[k] + (double)g.y * (double)ai[k]);
+            if (c0 <= 1) gx[1 - c0] = (double)a.n1 * ((double)g.x * (double)g1r[k] + (double)g.y * (double)g1i[k]);
+            gx[2 - c0] = (double)a.n2 * ((double)g.x * (double)g2r[k] + (double)g.y * (double)g2i[k]);
         } else {
             ((c_t<T> *)a.out)[pj] = cmk<T>(ar[k], ai[k]);
         }
@@ -651,6 +666,8 @@ inline PSArgs ps_args(const nfft3_plan_impl *p) {
     a.qinv = 0;
     a.fmask = 0;
     a.fstride = 0;
+    a.unit = p->unit;
+    a.gdim = p->dim;
     return a;
 }
 

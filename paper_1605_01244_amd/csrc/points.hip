@@ -445,6 +445,26 @@ z_scatter_kernel(const double *__restrict__ tx, const int *__restrict__ tperm, c
     stage_field<int>((int *)buf, v, sl, dest, nv, perm, 1, 0);
 }
 
+// ---- points of a lower-dimensional plan -----------------------------------
+// x3[j] = (0, .., 0, x[j][0], .., x[j][dim-1]): the leading unit axes take
+// coordinate 0 (their only frequency is 0, so any value gives the same sum).
+__global__ void __launch_bounds__(kPtThreads)
+widen_points_kernel(const double *__restrict__ x, int64_t M, int dim, double *__restrict__ x3) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 3 * M) return;
+    const int64_t j = e / 3;
+    const int c = (int)(e - 3 * j) - (3 - dim);
+    x3[e] = c >= 0 ? x[j * dim + c] : 0.0;
+}
+
+int launch_widen_points(hipStream_t s, int64_t M, int dim, const double *x, double *x3) {
+    if (M <= 0) return NFFT3_OK;
+    hipLaunchKernelGGL(widen_points_kernel, dim3((unsigned)((3 * M + kPtThreads - 1) / kPtThreads)),
+                       dim3(kPtThreads), 0, s, x, M, dim, x3);
+    NFFT3_LAUNCH_CHECK("widen_points_kernel");
+    return NFFT3_OK;
+}
+
 // ---- do the sorted points still describe x? ------------------------------
 // Sorted position q holds fold(x[perm[q]]) from the last sort.  If every
 // position still equals the fold of the caller's current coordinates (bit for

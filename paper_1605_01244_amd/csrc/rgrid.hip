@@ -215,10 +215,15 @@ static int launch_gemm(hipStream_t s, const void *A, const void *B, void *C, int
 }
 
 // ------------------------------------------------------------- host ----
+// Leading unit axes (N_d = M_d = 1: frequency 0 only, factor 1) make the
+// two- and one-dimensional forms; their products are skipped.
+static bool rgrid_unit(const nfft3_rgrid_impl *g, int d) { return g->N[d] == 1 && g->M[d] == 1; }
+
 static int rgrid_tables(nfft3_rgrid_impl *g, const double *const y[3]) {
     hipLaunchKernelGGL(rgrid_flag_kernel, dim3(1), dim3(64), 0, g->stream, g->flag);
     NFFT3_LAUNCH_CHECK("rgrid_flag_kernel");
     for (int d = 0; d < 3; ++d) {
+        if (rgrid_unit(g, d)) continue;          // no table: its product is skipped
         const int64_t cnt = g->M[d] * g->N[d];
         const unsigned blocks = (unsigned)((cnt + 255) / 256);
         const int trans = d == 2 ? 1 : 0;
@@ -240,12 +245,13 @@ static int rgrid_eval_t(nfft3_rgrid_impl *g, const void *fhat, void *out) {
     const int64_t N0 = g->N[0], N1 = g->N[1], N2 = g->N[2];
     const int64_t M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
     hipStream_t s = g->stream;
+    const bool u0 = rgrid_unit(g, 0), u1 = u0 && rgrid_unit(g, 1);
     // sum over k2: (N0 N1 x N2) (N2 x M2)
-    int rc = launch_gemm<T>(s, fhat, g->E[2], g->t1, N0 * N1, M2, N2, N2, M2, M2, 1, 0, 0, 0);
-    if (rc) return rc;
+    int rc = launch_gemm<T>(s, fhat, g->E[2], u1 ? out : g->t1, N0 * N1, M2, N2, N2, M2, M2, 1, 0, 0, 0);
+    if (rc || u1) return rc;
     // sum over k1, for every k0: (M1 x N1) (N1 x M2)
-    rc = launch_gemm<T>(s, g->E[1], g->t1, g->t2, M1, M2, N1, N1, M2, M2, N0, 0, N1 * M2, M1 * M2);
-    if (rc) return rc;
+    rc = launch_gemm<T>(s, g->E[1], g->t1, u0 ? out : g->t2, M1, M2, N1, N1, M2, M2, N0, 0, N1 * M2, M1 * M2);
+    if (rc || u0) return rc;
     // sum over k0: (M0 x N0) (N0 x M1 M2)
     return launch_gemm<T>(s, g->E[0], g->t2, out, M0, M1 * M2, N0, N0, M1 * M2, M1 * M2, 1, 0, 0, 0);
 }

@@ -90,10 +90,14 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
             const int zc = cell_frac<T>(xp[0], a.n0, f0[k]);
             const int yc = cell_frac<T>(xp[1], a.n1, f1);
             const int xc = cell_frac<T>(xp[2], a.n2, f2);
-            zlo[k] = zc - m + 1 - it.zbeg;
+            zlo[k] = (a.unit & 1) ? 0 : zc - m + 1 - it.zbeg;
             base[k] = 2 * ((yc - it.y0) * it.PX + (xc - it.x0));
             window_weights<T, W>(f1, coef, a.deg, w1[k]);
             window_weights<T, W>(f2, coef, a.deg, w2[k]);
+            if (a.unit & 2) {   // unit axis 1: every region row is grid row 0; weight 1 on one
+#pragma unroll
+                for (int r = 0; r < W; ++r) w1[k][r] = r == 0 ? (T)1 : (T)0;
+            }
             if constexpr (ROT) {
                 rot[k] = (((int)(threadIdx.x & 15) - (base[k] >> 1)) * pxinv) & 15;
                 rotate_rows<T, W, 16>(w1[k], rot[k]);
@@ -138,7 +142,7 @@ __global__ void __launch_bounds__(kPsThreads) spread_ps_kernel(PSArgs a) {
         for (int k = 0; k < PPT; ++k) {
             const int r0 = i - zlo[k];
             if (r0 >= 0 && r0 < W) {
-                const double w0 = (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
+                const double w0 = (a.unit & 1) ? 1.0 : (double)piece<T>(scoef + r0 * (a.deg + 1), a.deg, f0[k]);
                 const double vr = w0 * vr0[k], vi = w0 * vi0[k];
                 for (int r1 = 0; r1 < W; ++r1) {
                     const int rr = ROT ? (r1 + rot[k]) & 15 : r1;

@@ -54,10 +54,25 @@ def _plan(nf, N=(8, 8, 8), sigma=2.0, m=4, dtype=1):
     ((22, 8, 8), 2.0, 4, 1, -1),     # n = 44 = 4*11: factor 11 unsupported
     ((8, 8, 8), 2.0, 4, 5, -2),      # bad dtype
     ((2048, 8, 8), 2.0, 4, 1, -1),   # n > 2048
+    ((8, 1, 8), 2.0, 4, 1, -1),      # a unit axis that is not leading
+    ((8, 8, 1), 2.0, 4, 1, -1),
+    ((1, 8, 1), 2.0, 4, 1, -1),
 ])
 def test_plan_rejects_invalid_arguments(nf, N, sigma, m, dtype, code):
     rc, h = _plan(nf, N, sigma, m, dtype)
     assert rc == code
+
+
+@pytest.mark.parametrize("d,N,code", [
+    (0, (8,), -1), (4, (8, 8, 8, 8), -1),     # one to three axes
+    (1, (1,), -1), (2, (8, 1), -1),           # unit axes are not given explicitly
+    (1, (7,), -1), (2, (8, 4096), -1),        # odd N; n > 2048
+])
+def test_plan_nd_rejects_invalid_arguments(nf, d, N, code):
+    h = ctypes.c_void_p(123)
+    Narr = (ctypes.c_int64 * len(N))(*N)
+    assert nf.lib.nfft3_plan_nd(ctypes.byref(h), d, Narr, 2.0, 4, 1, None) == code
+    assert h.value is None
     assert h.value is None
 
 

@@ -268,6 +268,19 @@ def batched_sets(T: int = 64, sizes=(64, 96, 128), seed: int = 401, mmin: int = 
     return out
 
 
+def lowdim_case(d: int, N: int, M: int, seed: int = 801):
+    """One- or two-dimensional case (Appendix B's infft / infft2 sizes scaled
+    up): |k|^-2 random-phase coefficients on N^d, M uniform points (M, d)."""
+    rng = np.random.default_rng(seed)
+    shape = (int(N),) * d
+    ks = np.meshgrid(*[np.arange(N) - N // 2 for _ in range(d)], indexing="ij")
+    kk = np.sqrt(sum(k.astype(np.float64) ** 2 for k in ks))
+    theta = rng.uniform(0.0, 2.0 * math.pi, size=shape)
+    fhat = (np.cos(theta) + 1j * np.sin(theta)) / np.maximum(kk, 1.0) ** 2
+    x = np.random.default_rng(seed + 1).uniform(-0.5, 0.5, size=(int(M), d))
+    return fhat, x
+
+
 def clustered_grad_case(N: int = 128, M: int = 1_000_000):
     """Differentiation case: |k|^-2 coefficients, 16 clusters, random cotangent w."""
     fhat = powerlaw_coeffs((N, N, N), 701)
