@@ -252,7 +252,10 @@ def bench_rgrid(nf, torch, dev, workloads, stream):
     paper's 64^3 coefficients at a 64^3 grid, and 256^3 power-law
     coefficients at a nonuniform 321^3 grid; per form the median event time
     of nfft3_rgrid_eval and its rate against the dense MFMA peak of its dtype
-    (algorithmic flops 8 (N0 N1 N2 M2 + N0 N1 M1 M2 + N0 M0 M1 M2))."""
+    (algorithmic flops 8 (N0 N1 N2 M2 + N0 N1 M1 M2 + N0 M0 M1 M2), the
+    conventional count of four real products per complex multiply-add; the
+    kernel issues three (Gauss's form), so `issued_frac` reports 6/8 of that
+    rate, the matrix cores' own utilisation)."""
     res = {}
     r = np.random.default_rng(16)
     for name, N, M in (("64^3->64^3", (64, 64, 64), (64, 64, 64)), ("256^3->321^3", (256, 256, 256), (321, 321, 321))):
@@ -270,6 +273,7 @@ def bench_rgrid(nf, torch, dev, workloads, stream):
             ms = median(event_times(torch, stream, lambda: g.eval(fd, out=out), 10)[0])
             tfs = flops / (ms * 1e-3) / 1e12
             entry[form] = {"ms": ms, "tflops": tfs, "peak_tflops": peak, "frac": tfs / peak,
+                           "issued_frac": 0.75 * tfs / peak,
                            "points_per_s": M[0] * M[1] * M[2] / (ms * 1e-3)}
             log(f"rectilinear {name} {form}: {ms:.3f} ms, {tfs:.1f} TFLOP/s ({tfs / peak:.2f} of MFMA peak)")
             g.close()

@@ -278,7 +278,9 @@ int nfft3_gpe_destroy(nfft3_gpe_t g);
  * and nested sums of Sec. 2.1).  Exact up to rounding (no window): three
  * dense complex matrix products, one per axis, on the matrix cores (FP64 or
  * FP32 MFMA), with the E^d tables formed on the device from the coordinates.
- * Cost 8 (N0 N1 N2 M2 + N0 N1 M1 M2 + N0 M0 M1 M2) real flops. */
+ * Cost 8 (N0 N1 N2 M2 + N0 N1 M1 M2 + N0 M0 M1 M2) real flops counted as
+ * four real products per complex one; the matrix cores issue three (Gauss's
+ * form), 6/8 of that. */
 typedef struct nfft3_rgrid_s *nfft3_rgrid_t;
 
 /* Plan for N[3] coefficients (N_d even, 2 <= N_d <= 16384) and M[3] grid

@@ -49,6 +49,7 @@ def test_rgrid_matches_nested_sums(nf, N, M, dtype):
     got = _run(nf, N, ys, fh, dtype)
     ref = oracle.rgrid_eval(fh, *ys)
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.2e} rel-linf {li:.2e} (gate {gate(N, dtype):.1e})")
     assert l2 <= gate(N, dtype) and li <= gate(N, dtype), (l2, li)
 
 
@@ -64,6 +65,7 @@ def test_rgrid_regular_64_is_the_fft(nf, dtype):
     I = np.meshgrid(*[np.arange(n) - n // 2 for n in N], indexing="ij")
     ref = np.fft.fftn(np.fft.ifftshift(fh * (-1.0) ** (I[0] + I[1] + I[2])))
     l2, li = rel(got, ref)
+    log(f"  rel-l2 {l2:.2e} rel-linf {li:.2e} (gate {gate(N, dtype):.1e})")
     assert l2 <= gate(N, dtype) and li <= gate(N, dtype), (l2, li)
 
 
