@@ -503,65 +503,72 @@ int launch_points_equal(nfft3_plan_impl *p, int64_t M, const double *x, int *equ
     return NFFT3_OK;
 }
 
+__global__ void copy_int_kernel(const int *__restrict__ src, int *__restrict__ dst) { *dst = *src; }
+
 // ---- work items: greedy walks over segments of each tile column ----------
-// A tile column is cut into segments of kItemZ z-cells, one per thread;
-// within its segment a thread walks the cells: a new item starts when adding
-// the next cell would exceed maxpts points, and a cell holding more than
-// maxpts points becomes ceil(count/maxpts) items of its own.  Items never
-// cross a segment boundary, so none spans more than kItemZ cells.
-// WRITE=false counts the items of each (tile, segment), WRITE=true emits
-// (tile, p_lo, p_hi, 0) at the scanned offsets, i.e. in (tile, z) order.
-// (One walk per tile column made each step wait on the previous one; the
-// segments run side by side.)
-constexpr int kItemThreads = 64;         // one wave per workgroup: the walks spread over more CUs
+// A tile column is cut into segments of kItemZ z-cells, one wave per
+// segment: lane e loads the start of cell z0 + e (coalesced) and the cell
+// counts follow by a shuffle; the greedy walk over the cells then runs on
+// wave-uniform values (read lane by lane), and lane 0 writes the items: a new
+// item starts when adding the next cell would exceed maxpts points, and a
+// cell holding more than maxpts points becomes ceil(count/maxpts) items of
+// its own.  Items never cross a segment boundary, so none spans more than
+// kItemZ cells.  WRITE=false counts the items of each (tile, segment),
+// WRITE=true emits (tile, p_lo, p_hi, 0) at the scanned offsets, i.e. in
+// (tile, z) order.  (One thread per segment, walking 65 loaded starts, took
+// 3x longer: few waves, and every load a different line.)
+constexpr int kItemThreads = 64;         // one wave per segment
+static_assert(kItemZ == kItemThreads, "one lane per cell of a segment");
 
 template <bool WRITE>
 __global__ void __launch_bounds__(kItemThreads)
 items_kernel(const int *__restrict__ offsets, int copies, int ntiles, int n0, int nseg, int maxpts,
              int *__restrict__ item_count, const int *__restrict__ item_offset, int4 *__restrict__ items,
              int64_t cap, int *__restrict__ flag) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = blockIdx.x;
     if (q >= (int64_t)ntiles * nseg) return;
     const int tile = (int)(q / nseg), seg = (int)(q - (int64_t)tile * nseg);
     const int z0 = seg * kItemZ, z1 = min(n0, z0 + kItemZ);
+    const int lane = threadIdx.x;
     // bin (tile, z) spans offsets[(tile n0 + z) K] .. offsets[(tile n0 + z + 1) K],
     // K = copies counters per bin
     const int *g = offsets + (int64_t)tile * n0 * copies;
-    int k = 0;
+    const int oz = g[(int64_t)min(z0 + lane, z1) * copies];
+    const int oend = g[(int64_t)z1 * copies];
+    // (the shuffle runs on every lane: under a branch, the last lane would
+    // not take part, and its neighbour would read nothing from it)
+    const int oright = __shfl_down(oz, 1);
+    const int onext = lane + 1 < kItemThreads ? oright : oend;
+    const int cnt = z0 + lane < z1 ? onext - oz : 0;
     const int64_t w = WRITE ? item_offset[q] : 0;
-    int cur = 0, p_start = 0;
-    // the segment's kItemZ + 1 bin starts, all loads in flight together
-    int o[kItemZ + 1];
-#pragma unroll
-    for (int e = 0; e <= kItemZ; ++e) o[e] = g[(int64_t)min(z0 + e, z1) * copies];
-#pragma unroll
-    for (int e = 0; e < kItemZ; ++e) {
-        const int z = z0 + e;
-        const int oz = o[e];
-        const int c = o[e + 1] - oz;
-        if (z >= z1 || c == 0) continue;
+    const bool writer = WRITE && lane == 0;
+    int k = 0, cur = 0, p_start = 0;
+    for (int e = 0; e < z1 - z0; ++e) {
+        const int c = __builtin_amdgcn_readlane(cnt, e);
+        if (c == 0) continue;
+        const int o = __builtin_amdgcn_readlane(oz, e);
         if (cur > 0 && cur + c > maxpts) {
-            if (WRITE && w + k < cap) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
+            if (writer && w + k < cap) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
             ++k;
             cur = 0;
         }
         if (c > maxpts) {     // a dense cell on its own
             for (int s0 = 0; s0 < c; s0 += maxpts) {
-                if (WRITE && w + k < cap) items[w + k] = make_int4(tile, oz + s0, oz + min(c, s0 + maxpts), 0);
+                if (writer && w + k < cap) items[w + k] = make_int4(tile, o + s0, o + min(c, s0 + maxpts), 0);
                 ++k;
             }
             continue;
         }
-        if (cur == 0) p_start = oz;
+        if (cur == 0) p_start = o;
         cur += c;
     }
     if (cur > 0) {
-        if (WRITE && w + k < cap) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
+        if (writer && w + k < cap) items[w + k] = make_int4(tile, p_start, p_start + cur, 0);
         ++k;
     }
-    if (!WRITE) item_count[q] = k;
+    if (!WRITE && lane == 0) item_count[q] = k;
     // the list is sized by max_items; should it ever be short, report it
-    if (WRITE && w + k > cap) atomicOr(flag, 4);
+    if (writer && w + k > cap) atomicOr(flag, 4);
 }
 
 // Items of a tiling with ntiles tile columns of n0 cells for M points, at
@@ -693,7 +700,7 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x, int *flag_
     }
     const int nseg = (int)((g.in0 + kItemZ - 1) / kItemZ);
     const int64_t nws = (int64_t)ntiles * nseg;
-    const unsigned tb = (unsigned)((nws + kItemThreads - 1) / kItemThreads);
+    const unsigned tb = (unsigned)nws;        // one wave per (tile, segment)
     hipLaunchKernelGGL((items_kernel<false>), dim3(tb), dim3(kItemThreads), 0, s, p->bins.offsets, copies, ntiles, g.in0, nseg,
                        p->sub.maxpts, p->bins.tile_items, (const int *)nullptr, (int4 *)nullptr, (int64_t)0, p->flag);
     NFFT3_LAUNCH_CHECK("items_kernel");
@@ -704,11 +711,13 @@ int launch_set_points(nfft3_plan_impl *p, int64_t M, const double *x, int *flag_
                        p->flag);
     NFFT3_LAUNCH_CHECK("items_kernel");
     // the item count sizes the window-sum launches; the flag reports
-    // non-finite points: one synchronisation for both
-    int nitems = 0, flag = 0;
-    NFFT3_HIP_TRY(hipMemcpyAsync(&nitems, p->bins.tile_item_off + nws, sizeof(int), hipMemcpyDeviceToHost, s));
-    NFFT3_HIP_TRY(hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    // non-finite points: one copy and one synchronisation for both
+    hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, p->bins.tile_item_off + nws, p->flag + 2);
+    NFFT3_LAUNCH_CHECK("copy_int_kernel");
+    int words[3] = {0, 0, 0};
+    NFFT3_HIP_TRY(hipMemcpyAsync(words, p->flag, sizeof(words), hipMemcpyDeviceToHost, s));
     NFFT3_HIP_TRY(hipStreamSynchronize(s));
+    const int nitems = words[2], flag = words[0];
     if (flag & 4) return NFFT3_ERR_INVALID_ARG;    // item list too short (never expected)
     p->sub.count = nitems;
     *flag_out = flag;

@@ -440,3 +440,21 @@ def test_derivative_fields(nf, dtype):
     out5 = p.trafo_fields(to_dev(fh, dtype), 5).cpu().numpy()
     assert out5.shape[0] == 3
     assert np.allclose(out5[1], out[1]) and np.allclose(out5[2], out[3])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("N", [(32, 32, 32), (64, 8, 8), (48, 16, 16)])
+def test_full_item_segments(nf, N, dtype):
+    """Grids whose z-axis fills whole 64-cell segments of the work-item walk
+    (n0 = 64, 128) and one that leaves a partial segment (n0 = 96): every
+    cell's count comes from its neighbour's start, up to the segment's last."""
+    m = 8 if dtype == "c128" else 4
+    fh = rand_coeffs(N, 140)
+    x = np.concatenate([rand_points(1500, 141),
+                        workloads.wrap(0.1 + 0.01 * np.random.default_rng(142).standard_normal((1500, 3)))])
+    log(f"full item segments N={N} {dtype}")
+    p = make_plan(nf, N, m, dtype)
+    p.set_points(to_dev(x))
+    got = p.trafo(to_dev(fh, dtype)).cpu().numpy()
+    l2, li = rel(got, oracle.ndft_trafo(fh, x))
+    assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (l2, li)
