@@ -316,7 +316,8 @@ constexpr size_t kColsLdsMaxGeneric = 80 * 1024;
 // radix plan, and make_col_args takes the column count from here, so host
 // and device agree.
 constexpr bool static_fft_len(int n) {
-    return n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512;
+    return n == 64 || n == 80 || n == 96 || n == 128 || n == 160 || n == 192 || n == 256 || n == 320 || n == 384 ||
+           n == 512;
 }
 constexpr int st_lines_fit(int n, int vmax, int cap, int nthreads) {
     int best = 1;
@@ -576,7 +577,7 @@ __device__ __forceinline__ void cols_body_s(const ColArgs &a, int bx, int by, un
 
 // The lengths the compile-time engine is instantiated for (2^a 3^b 5^c
 // oversampled lengths of the common coefficient sizes).
-#define NFFT3_STATIC_LENGTHS(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define NFFT3_STATIC_LENGTHS(X) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
 // Largest number of lines such that every stage fits VMAX values per thread.
 inline int lines_fit(const FftAxisPlan &f, int vmax, int cap, int nthreads) {

@@ -34,7 +34,8 @@ def make_plan(nf, N, m, dtype, sigma=2.0):
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("N,sigma,m", [((8, 12, 16), 2.0, 3), ((32, 32, 32), 2.0, 6), ((16, 24, 20), 1.5, 4),
                                        ((6, 10, 4), 2.0, 2), ((32, 64, 256), 2.0, 4), ((128, 2, 64), 2.0, 1),
-                                       ((48, 96, 192), 2.0, 4), ((14, 28, 42), 2.0, 4), ((56, 70, 98), 2.0, 5)])
+                                       ((48, 96, 192), 2.0, 4), ((14, 28, 42), 2.0, 4), ((56, 70, 98), 2.0, 5),
+                                       ((40, 80, 160), 2.0, 4)])
 def test_stage_grid_matches_fft_of_deconvolved(nf, N, sigma, m, dtype):
     """Deconvolve + zero-pad + 3-D FFT equals numpy fftn of the textbook
     deconvolved array (GPU window normalised: factor phi(0)^3); lengths with
@@ -344,7 +345,7 @@ def test_empty_points_and_errors(nf):
 # ------------------------------------------------------------- adjoint ----
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("N", [(16, 12, 20), (32, 64, 128), (96, 48, 32)])
+@pytest.mark.parametrize("N", [(16, 12, 20), (32, 64, 128), (96, 48, 32), (40, 160, 80)])
 def test_adjoint_dot_product_and_direct_sum(nf, N, dtype):
     m = 8 if dtype == "c128" else 4
     fh = rand_coeffs(N, 40)
