@@ -31,6 +31,13 @@ __global__ void __launch_bounds__(kPsThreads) interp_ps_kernel(PSArgs a) {
     interp_body<T, W, PPT>(a, xcd_item(blockIdx.x, gridDim.x), smem_raw);
 }
 
+// one-dimensional plans (unit axes 0 and 1): one stencil row per point
+template <typename T, int W, int PPT>
+__global__ void __launch_bounds__(kPsThreads) interp_row1_kernel(PSArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    interp_body<T, W, PPT, true>(a, xcd_item(blockIdx.x, gridDim.x), smem_raw);
+}
+
 // ------------------------------------------------------- grad, fields ----
 // The interp body in its derivative modes (rotated, conflict-free reads), one
 // point per thread: items of more points are taken 256 at a time.
@@ -58,6 +65,13 @@ static int interp_ppt(nfft3_plan_impl *p, const void *grid, void *f) {
     a.grid = grid;
     a.out = f;
     const size_t lds = interp_lds(p, a);
+    if ((p->unit & 3) == 3) {
+        allow_lds((const void *)interp_row1_kernel<T, W, PPT>, lds);
+        hipLaunchKernelGGL((interp_row1_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
+                           p->stream, a);
+        NFFT3_LAUNCH_CHECK("interp_row1_kernel");
+        return NFFT3_OK;
+    }
     allow_lds((const void *)interp_ps_kernel<T, W, PPT>, lds);
     hipLaunchKernelGGL((interp_ps_kernel<T, W, PPT>), dim3((unsigned)p->sub.count), dim3(kPsThreads), lds,
                        p->stream, a);

@@ -152,7 +152,7 @@ __device__ __forceinline__ int xcd_item(int b, int G) {
 }
 
 // Geometry of the points [lo, hi) (sorted indices) of tile `tile`.
-__device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int lo, int hi) {
+__device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int lo, int hi, bool rows1 = false) {
     PSItem it;
     const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
     it.y0 = ty * a.By;
@@ -169,7 +169,7 @@ __device__ __forceinline__ PSItem ps_range(const PSArgs &a, int m, int tile, int
         it.zbeg = 0;
         it.nplanes = 1;
     }
-    it.PY = a.By + 2 * m - 1;
+    it.PY = rows1 ? 1 : a.By + 2 * m - 1;    // rows1: only the region's first row is read
     it.PX = a.Bx + 2 * m - 1;
     it.psz = it.PY * it.PX;
     it.PXp = a.pxp ? a.pxp : it.PX;
@@ -344,7 +344,10 @@ __device__ __forceinline__ bool interp_walk_down(int item, int nplanes, int W) {
 // reads are the same.  kModeGrad writes grad_x[j, d] = n_d Re(conj(G_j) D_d),
 // kModeFields the field and the derivative fields n_d D_d of a.fmask.
 
-template <typename T, int W, int PPT, int MODE>
+// ROW1 (value mode of a one-dimensional plan, unit axes 0 and 1): every
+// stencil row of the region is grid row 0 and only the first carries weight
+// 1, so one row is staged and read, without rotation.
+template <typename T, int W, int PPT, int MODE, bool ROW1 = false>
 __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, const int4 item,
                                              unsigned char *smem_raw) {
     constexpr int m = W / 2;
@@ -356,7 +359,8 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
     constexpr int NW = NR * EPU;                   // column weights per row
     constexpr int D = 16 / cgcd(W, 16);            // cosets of bank groups
     constexpr int NT = 16 / D;                     // distinct rotations
-    const PSItem it = ps_range(a, m, item.x, item.y, item.z);
+    static_assert(!ROW1 || MODE == kModeValue, "one-row walk in the value mode only");
+    const PSItem it = ps_range(a, m, item.x, item.y, item.z, ROW1);
     const int RU = it.PXp / EPU;
     const int bufsz = it.PY * it.PXp;
     c_t<T> *buf0 = reinterpret_cast<c_t<T> *>(smem_raw);
@@ -411,7 +415,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
                 window_weights_d<T, W>(f1, coef, a.deg, w1[k], d1[k]);
                 window_weights_d<T, W>(f2, coef, a.deg, w2, e2);
             } else {
-                window_weights<T, W>(f1, coef, a.deg, w1[k]);
+                if constexpr (!ROW1) window_weights<T, W>(f1, coef, a.deg, w1[k]);
                 window_weights<T, W>(f2, coef, a.deg, w2);
             }
             if (a.unit & 2) {   // unit axis 1: every region row is grid row 0; weight 1 on one
@@ -447,8 +451,8 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
         }
         const int target = D == 2 ? cs + 2 * ((rank & 3) + 4 * ((lane >> 3) & 1)) : cs + D * (rank & (NT - 1));
         const int delta = (target - u) & 15;   // a multiple of D
-        const int t = ((delta / D) * a.qinv) & (NT - 1);
-        rotate_rows<T, W, NT>(w1[k], t);
+        const int t = ROW1 ? 0 : ((delta / D) * a.qinv) & (NT - 1);
+        if constexpr (!ROW1) rotate_rows<T, W, NT>(w1[k], t);
         if constexpr (GRAD) rotate_rows<T, W, NT>(d1[k], t);
         tt[k] = t;
         ub0[k] = u + t * RU;
@@ -512,7 +516,7 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
                 constexpr int S = NR / CH;             // chunks per row
                 // (the derivative mode holds twice the weights: one chunk ahead)
                 constexpr int LA = GRAD ? (interp_lookahead<T>(CH) > 0 ? 1 : 0) : interp_lookahead<T>(CH);
-                constexpr int NQ = W * S;
+                constexpr int NQ = ROW1 ? S : W * S;      // ROW1: the first row only
                 U g[LA + 1][CH];
 #pragma unroll
                 for (int q = 0; q < LA; ++q) {
@@ -556,8 +560,13 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
                         }
                     }
                     if (q % S == S - 1) {
-                        sr += w1[k][q / S] * cr;
-                        si += w1[k][q / S] * ci;
+                        if constexpr (ROW1) {
+                            sr += cr;
+                            si += ci;
+                        } else {
+                            sr += w1[k][q / S] * cr;
+                            si += w1[k][q / S] * ci;
+                        }
                         if constexpr (GRAD) {
                             ur += d1[k][q / S] * cr;
                             ui += d1[k][q / S] * ci;
@@ -629,9 +638,9 @@ __device__ __forceinline__ void interp_range(const PSArgs &a, int item_index, co
 }
 
 
-template <typename T, int W, int PPT>
+template <typename T, int W, int PPT, bool ROW1 = false>
 __device__ __forceinline__ void interp_body(const PSArgs &a, int item_index, unsigned char *smem_raw) {
-    interp_range<T, W, PPT, kModeValue>(a, item_index, a.items[item_index], smem_raw);
+    interp_range<T, W, PPT, kModeValue, ROW1>(a, item_index, a.items[item_index], smem_raw);
 }
 
 // Derivative modes: one point per thread (to stay within two waves per SIMD
