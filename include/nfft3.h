@@ -65,7 +65,8 @@ enum nfft3_status {
     NFFT3_ERR_NONFINITE = -5,   /* a point coordinate is NaN or infinite         */
     NFFT3_ERR_HIP = -6,         /* HIP runtime error (see nfft3_last_hip_error)  */
     NFFT3_ERR_NULL = -7,        /* NULL plan or NULL required pointer            */
-    NFFT3_ERR_CAPACITY = -8     /* batch too large for nfft3_batch_trafo_noalloc */
+    NFFT3_ERR_CAPACITY = -8,    /* batch too large for nfft3_batch_trafo_noalloc */
+    NFFT3_ERR_TIMEOUT = -9      /* a nfft3_batch_trafo_queue wait hit its limit  */
 };
 
 /* Create a plan for coefficient sizes N[0..2] (host array).
@@ -177,6 +178,23 @@ int nfft3_trafo_fields(nfft3_plan_t p, const void *fhat_dev, void *out_dev, int 
  * (the launch descriptors are staged from host memory). */
 int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
                       void *const *out_dev, int deriv_mask);
+
+/* nfft3_batch_trafo as ONE launch: persistent workgroups take tickets over
+ * (transform, stage, tile) from a device counter, the tickets laid out
+ * stage-major, and a task waits (spinning on a device counter) only for the
+ * previous stage of its own transform; the stages' bodies are those of
+ * nfft3_batch_trafo (the column passes in 256-thread tiles of fewer columns,
+ * each line's arithmetic unchanged), so the results equal it bit for bit.
+ * Same arguments; additionally every plan's three oversampled lengths must
+ * be ones the library's compile-time FFT engine covers (64, 80, 96, 128,
+ * 160, 192, 256, 320, 384, 512), else NFFT3_ERR_INVALID_ARG before any work.
+ * Each wait is bounded by NFFT3_QUEUE_WAIT_US microseconds of wall clock
+ * (environment, read per call; default 2000000): a wait past it abandons the
+ * batch (the outputs are then incomplete) and returns NFFT3_ERR_TIMEOUT.
+ * Allocates its descriptor buffer as nfft3_batch_trafo does (shared with it,
+ * under the same per-GPU lock); synchronises before it returns. */
+int nfft3_batch_trafo_queue(int T, const nfft3_plan_t *plans, const void *const *fhat_dev,
+                            void *const *out_dev, int deriv_mask);
 
 /* nfft3_batch_trafo without device allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,

@@ -439,14 +439,15 @@ class RectGrid:
 
 
 def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask: int = 0,
-                out: Sequence[torch.Tensor] | None = None, allocate: bool = True):
+                out: Sequence[torch.Tensor] | None = None, allocate: bool = True, queue: bool = False):
     """Evaluate every plan's coefficients (and derivative fields) together:
     per stage one launch per transform length over all (plan, field) pairs
     of that length (the window sums: one launch).  Returns a list of
     (1 + popcount(mask), M_t) tensors (`out`, when given: contiguous tensors
     of those shapes).  allocate=False calls nfft3_batch_trafo_noalloc, which
     allocates no device memory (the plans must already hold their field
-    grids)."""
+    grids); queue=True calls nfft3_batch_trafo_queue, the whole batch as one
+    work-queue launch (same results)."""
     T = len(plans)
     if T != len(fhats):
         raise ValueError("one coefficient array per plan")
@@ -468,7 +469,11 @@ def batch_trafo(plans: Sequence[Plan], fhats: Sequence[torch.Tensor], deriv_mask
     H = (ctypes.c_void_p * T)(*[p._h.value for p in plans])
     F = (ctypes.c_void_p * T)(*[f.data_ptr() for f in fh])
     O = (ctypes.c_void_p * T)(*[o.data_ptr() for o in outs])
-    if allocate:
+    if queue:
+        if not allocate:
+            raise ValueError("the work-queue form allocates its descriptor buffer")
+        check(lib.nfft3_batch_trafo_queue(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo_queue")
+    elif allocate:
         check(lib.nfft3_batch_trafo(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo")
     else:
         check(lib.nfft3_batch_trafo_noalloc(T, H, F, O, int(deriv_mask)), "nfft3_batch_trafo_noalloc")

@@ -25,6 +25,7 @@ STATUS = {
     -6: "NFFT3_ERR_HIP",
     -7: "NFFT3_ERR_NULL",
     -8: "NFFT3_ERR_CAPACITY",
+    -9: "NFFT3_ERR_TIMEOUT",
 }
 
 
@@ -59,6 +60,7 @@ def _load() -> ctypes.CDLL:
         "nfft3_trafo_fields": ([vp, vp, vp, ci], ci),
         "nfft3_batch_trafo": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
         "nfft3_batch_trafo_noalloc": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
+        "nfft3_batch_trafo_queue": ([ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ci], ci),
         "nfft3_infft3": ([vp, dp, dp, vp, i64, vp, vp], ci),
         "nfft3_tube_refine": ([vp, dp, dp, vp, ci, dp, i64, vp, vp, i64p], ci),
         "nfft3_gpe_create": ([ctypes.POINTER(vp), i64p, dp, dp, ci, vp], ci),

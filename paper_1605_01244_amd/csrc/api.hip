@@ -538,7 +538,7 @@ int nfft3_grad_points(nfft3_plan_t p, const void *fhat, const void *G, double *g
 }
 
 static int batch_common(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out, int mask,
-                        bool noalloc) {
+                        int form) {
     if (T < 0 || mask < 0 || mask > 7) return NFFT3_ERR_INVALID_ARG;
     if (T == 0) return NFFT3_OK;
     if (!plans || !fhat || !out) return NFFT3_ERR_NULL;
@@ -555,16 +555,20 @@ static int batch_common(int T, const nfft3_plan_t *plans, const void *const *fha
             if (plans[u] == plans[t]) return NFFT3_ERR_INVALID_ARG;
     }
     std::vector<nfft3_plan_impl *> pl(plans, plans + T);
-    return launch_batch(T, pl.data(), fhat, out, mask, noalloc);
+    return launch_batch(T, pl.data(), fhat, out, mask, form);
 }
 
 int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out, int mask) {
-    return batch_common(T, plans, fhat, out, mask, false);
+    return batch_common(T, plans, fhat, out, mask, kBatchLaunches);
+}
+
+int nfft3_batch_trafo_queue(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out, int mask) {
+    return batch_common(T, plans, fhat, out, mask, kBatchQueue);
 }
 
 int nfft3_batch_trafo_noalloc(int T, const nfft3_plan_t *plans, const void *const *fhat, void *const *out,
                               int mask) {
-    return batch_common(T, plans, fhat, out, mask, true);
+    return batch_common(T, plans, fhat, out, mask, kBatchNoAlloc);
 }
 
 const char *nfft3_strerror(int code) {
@@ -578,6 +582,7 @@ const char *nfft3_strerror(int code) {
         case NFFT3_ERR_HIP: return "HIP runtime error";
         case NFFT3_ERR_NULL: return "NULL plan or pointer";
         case NFFT3_ERR_CAPACITY: return "launch descriptors exceed the static scratch of the no-allocation call";
+        case NFFT3_ERR_TIMEOUT: return "a work-queue wait exceeded its time limit (the batch was abandoned)";
         default: return "unknown status";
     }
 }

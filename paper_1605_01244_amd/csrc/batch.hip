@@ -6,37 +6,32 @@
 // transform per plan whose window sums also write the derivative fields
 // (window derivative, as nfft3_trafo_fields).  A transform has four stages: the row pass
 // (deconvolve + zero-pad + FFT along axis 2), the column passes along axes 1
-// and 0, and the window sums.  Each FFT stage runs as one launch per distinct
-// transform length along its axis (a kernel specialised for that length, or
-// one generic launch for lengths the compile-time engine does not cover),
-// the window sums as one launch; each launch covers the work items (row
-// blocks, column tiles, point items) of every transform in its group:
-// workgroup b finds its transform by a binary search in the group's prefix
-// table of item counts and runs item b - first[t] with that transform's
-// arguments.  Kernel boundaries order the stages, so no workgroup ever waits
-// on another.  The stage bodies and launch shapes are the ones of the
-// single-plan kernels, so a batched result equals the sequential one bit for
-// bit.  (A single kernel over all lengths holds every specialisation's code
-// and ran several times slower.)
+// and 0, and the window sums.
+//
+// Two forms run the same stage bodies.  Per-length launches: each FFT stage
+// runs as one launch per distinct transform length along its axis (a kernel
+// specialised for that length, or one generic launch for lengths the
+// compile-time engine does not cover), the window sums as one launch; each
+// launch covers the work items (row blocks, column tiles, point items) of
+// every transform in its group: workgroup b finds its transform by a binary
+// search in the group's prefix table of item counts and runs item b -
+// first[t] with that transform's arguments.  Kernel boundaries order the
+// stages, so no workgroup ever waits on another.  The stage bodies and
+// launch shapes are the ones of the single-plan kernels, so a batched result
+// equals the sequential one bit for bit.  (A single kernel over all lengths
+// holds every specialisation's code and ran several times slower.)
+// Work queue: one launch of persistent workgroups over (transform, stage,
+// tile) tickets (queue_impl.h); the same bodies (the column passes with 256
+// threads and fewer columns per tile, which leaves each line's arithmetic
+// unchanged), so its results equal the per-length form's bit for bit.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
-#include "fft_dev.h"
-#include "interp_dev.h"
+#include "batch_dev.h"
 
 namespace nfft3 {
-
-constexpr int kStages = 4;
-constexpr int kBRowThreads = 256;
-
-struct BatchXform {
-    RowArgs rows;
-    ColArgs c1, c0;
-    PSArgs ip;
-    int gx1, gx0;
-    int ntile[kStages];
-};
 
 // transform of block b: last t with first[t] <= b (first has X + 1 entries)
 __device__ __forceinline__ int batch_find(const int *__restrict__ first, int X, int b) {
@@ -174,9 +169,129 @@ static int scratch_address(int dev, void **ptr) {
     return NFFT3_OK;
 }
 
+// fills the queue's control words (a kernel, not a memset: safe under capture)
+__global__ void __launch_bounds__(256) queue_reset_kernel(unsigned *ctl, int n) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) ctl[i] = 0;
+}
+
+// wall-clock ticks a queue wait may last: NFFT3_QUEUE_WAIT_US microseconds
+// (default 2 s)
+static int queue_wait_ticks(int dev, unsigned long long *ticks) {
+    int khz = 0;
+    NFFT3_HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    double us = 2e6;
+    if (const char *e = std::getenv("NFFT3_QUEUE_WAIT_US")) us = std::max(0.0, std::atof(e));
+    *ticks = (unsigned long long)(us * 1e-3 * (double)std::max(khz, 1));
+    return NFFT3_OK;
+}
+
+// The work-queue form: segments of tickets stage-major (every transform's
+// row pass, then every axis-1 pass, ...), each waiting for the previous
+// stage of its own transform; one launch (after the control words are
+// cleared).  Uses the allocating call's descriptor buffer; the caller holds
+// the GPU's lock.
+template <typename T, int W, int PPT>
+static int queue_launch(const std::vector<BatchXform> &xf, size_t lds_ip, bool fields, hipStream_t stream,
+                        int dev) {
+    const int X = (int)xf.size();
+    std::vector<QSeg> segs;
+    int64_t total = 0;
+    size_t lds = lds_ip;
+    // tiles per ticket, per stage
+    int cus = 0;
+    NFFT3_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t stage_tiles[kStages] = {0, 0, 0, 0};
+    for (const BatchXform &b : xf)
+        for (int s = 0; s < kStages; ++s) stage_tiles[s] += std::max(b.ntile[s], 0);
+    int chunk[kStages];
+    const int64_t per = (int64_t)kQTicketsPerCu * std::max(cus, 1);
+    for (int s = 0; s < 3; ++s) chunk[s] = (int)std::min<int64_t>(kQChunkFftMax, std::max<int64_t>(1, stage_tiles[s] / per));
+    chunk[3] = (sizeof(T) == 4 && stage_tiles[3] >= 8 * per) ? 2 : 1;
+    auto chunk_of = [&](int s) { return chunk[s]; };
+    auto tickets = [&](int ntile, int s) { return (ntile + chunk_of(s) - 1) / chunk_of(s); };
+    for (int s = 0; s < kStages; ++s) {
+        for (int x = 0; x < X; ++x) {
+            const BatchXform &b = xf[x];
+            if (s == 0) lds = std::max({lds, row_lds<T>(b.rows), col_lds<T>(b.c1), col_lds<T>(b.c0)});
+            if (b.ntile[s] <= 0) continue;
+            QSeg g;
+            g.first = (int)total;
+            g.x = x;
+            g.stage = s;
+            g.kind = s == 0 ? b.rows.n : s == 1 ? b.c1.n : s == 2 ? b.c0.n : 0;
+            g.dep = -1;
+            g.need = 0;
+            g.ntile = b.ntile[s];
+            g.chunk = chunk_of(s);
+            for (int r = s - 1; r >= 0; --r) {
+                if (b.ntile[r] > 0) {
+                    g.dep = 4 * x + r;
+                    g.need = tickets(b.ntile[r], r);
+                    break;
+                }
+            }
+            segs.push_back(g);
+            total += tickets(b.ntile[s], s);
+        }
+    }
+    if (total == 0) return NFFT3_OK;
+    if (total > INT32_MAX) return NFFT3_ERR_INVALID_ARG;
+    std::vector<int> tseg((size_t)total);
+    for (size_t i = 0; i < segs.size(); ++i) {
+        const int end = i + 1 < segs.size() ? segs[i + 1].first : (int)total;
+        std::fill(tseg.begin() + segs[i].first, tseg.begin() + end, (int)i);
+    }
+    const size_t off_segs = ((sizeof(BatchXform) * X + 255) / 256) * 256;
+    const size_t off_tseg = ((off_segs + sizeof(QSeg) * segs.size() + 255) / 256) * 256;
+    const size_t off_ctl = ((off_tseg + sizeof(int) * tseg.size() + 255) / 256) * 256;
+    const int nctl = kQDone + 4 * X;
+    const size_t need = off_ctl + sizeof(unsigned) * nctl;
+    DescBuf &d = g_desc[dev];
+    if (need > d.cap) {
+        // the previous call on this GPU synchronised before it released the lock
+        (void)hipFree(d.buf);
+        d.buf = nullptr;
+        d.cap = 0;
+        NFFT3_HIP_TRY(hipMalloc(&d.buf, need));
+        d.cap = need;
+    }
+    char *base = (char *)d.buf;
+    QueueLaunch q;
+    q.args.xf = (const BatchXform *)base;
+    q.args.segs = (const QSeg *)(base + off_segs);
+    q.args.tseg = (const int *)(base + off_tseg);
+    q.args.ctl = (unsigned *)(base + off_ctl);
+    q.args.nseg = (int)segs.size();
+    q.args.total = (int)total;
+    int rc = queue_wait_ticks(dev, &q.args.wait_ticks);
+    if (rc) return rc;
+    q.lds = lds;
+    q.W = W;
+    q.ppt = PPT;
+    q.fields = fields;
+    NFFT3_HIP_TRY(hipMemcpyAsync(base, xf.data(), sizeof(BatchXform) * X, hipMemcpyHostToDevice, stream));
+    NFFT3_HIP_TRY(hipMemcpyAsync(base + off_segs, segs.data(), sizeof(QSeg) * segs.size(), hipMemcpyHostToDevice,
+                                 stream));
+    NFFT3_HIP_TRY(hipMemcpyAsync(base + off_tseg, tseg.data(), sizeof(int) * tseg.size(), hipMemcpyHostToDevice,
+                                 stream));
+    hipLaunchKernelGGL(queue_reset_kernel, dim3((unsigned)std::min((nctl + 255) / 256, 1024)), dim3(256), 0,
+                       stream, q.args.ctl, nctl);
+    NFFT3_LAUNCH_CHECK("queue_reset_kernel");
+    rc = sizeof(T) == 8 ? launch_queue_f64(q, stream) : launch_queue_f32(q, stream);
+    unsigned aborted = 0;
+    if (rc == NFFT3_OK)
+        NFFT3_HIP_TRY(hipMemcpyAsync(&aborted, q.args.ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+    // the host vectors above are copied from pageable memory; make sure the
+    // copies are done before they go away
+    NFFT3_HIP_TRY(hipStreamSynchronize(stream));
+    if (rc) return rc;
+    return aborted ? NFFT3_ERR_TIMEOUT : NFFT3_OK;
+}
+
 template <typename T, int W, int PPT>
 static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask,
-                        bool noalloc) {
+                        int form) {
+    const bool noalloc = form == kBatchNoAlloc, queue = form == kBatchQueue;
     const int dev = plans[0]->device;
     if (dev < 0 || dev >= kMaxDevices) return NFFT3_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(g_batch_mu[dev]);
@@ -235,8 +350,22 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
             b.ntile[2] = b.gx0 * (int)p->n[1];
             b.ntile[3] = (p->M > 0) ? (int)p->sub.count : 0;
             lds_ip = std::max(lds_ip, interp_lds(p, b.ip));
+            if (queue) {
+                // the queue's column tiles (256 threads); compile-time lengths only
+                for (int ax = 0; ax < 3; ++ax)
+                    if (!static_fft_len((int)p->n[ax])) return NFFT3_ERR_INVALID_ARG;
+                if (b.rows.lpw != static_rows_nl<T>(b.rows.n)) return NFFT3_ERR_INVALID_ARG;
+                b.c1.C = queue_cols_nl<T>(b.c1.n);
+                b.c0.C = queue_cols_nl<T>(b.c0.n);
+                if (b.c1.C > b.c1.ncols || b.c0.C > b.c0.ncols) return NFFT3_ERR_INVALID_ARG;
+                b.gx1 = col_grid_x(b.c1);
+                b.gx0 = col_grid_x(b.c0);
+                b.ntile[1] = b.gx1 * (int)p->N[0];
+                b.ntile[2] = b.gx0 * (int)p->n[1];
+            }
         }
     }
+    if (queue) return queue_launch<T, W, PPT>(xf, lds_ip, der_fields, stream, dev);
     // groups: per FFT stage one per distinct axis length (static lengths
     // only when the pass uses the compile-time engine's line counts), one for
     // the window sums
@@ -342,15 +471,15 @@ static int batch_launch(int T_, nfft3_plan_impl *const *plans, const void *const
 
 template <typename T, int W>
 static int batch_w(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask,
-                   bool noalloc) {
+                   int form) {
     for (int t = 0; t < T_; ++t)
         if (plans[t]->sub.maxpts != plans[0]->sub.maxpts) return NFFT3_ERR_INVALID_ARG;
     if constexpr (W > 16) {
         return NFFT3_ERR_INVALID_ARG;
     } else {
         switch (plans[0]->sub.maxpts / kPsThreads) {
-            case 1: return batch_launch<T, W, 1>(T_, plans, fhat, out, mask, noalloc);
-            case 2: return batch_launch<T, W, 2>(T_, plans, fhat, out, mask, noalloc);
+            case 1: return batch_launch<T, W, 1>(T_, plans, fhat, out, mask, form);
+            case 2: return batch_launch<T, W, 2>(T_, plans, fhat, out, mask, form);
             default: return NFFT3_ERR_INVALID_ARG;
         }
     }
@@ -358,19 +487,19 @@ static int batch_w(int T_, nfft3_plan_impl *const *plans, const void *const *fha
 
 #define NFFT3_BATCH_M(T)                                          \
     switch (plans[0]->m) {                                        \
-        case 1: return batch_w<T, 2>(T_, plans, fhat, out, mask, noalloc);  \
-        case 2: return batch_w<T, 4>(T_, plans, fhat, out, mask, noalloc);  \
-        case 3: return batch_w<T, 6>(T_, plans, fhat, out, mask, noalloc);  \
-        case 4: return batch_w<T, 8>(T_, plans, fhat, out, mask, noalloc);  \
-        case 5: return batch_w<T, 10>(T_, plans, fhat, out, mask, noalloc); \
-        case 6: return batch_w<T, 12>(T_, plans, fhat, out, mask, noalloc); \
-        case 7: return batch_w<T, 14>(T_, plans, fhat, out, mask, noalloc); \
-        case 8: return batch_w<T, 16>(T_, plans, fhat, out, mask, noalloc); \
+        case 1: return batch_w<T, 2>(T_, plans, fhat, out, mask, form);  \
+        case 2: return batch_w<T, 4>(T_, plans, fhat, out, mask, form);  \
+        case 3: return batch_w<T, 6>(T_, plans, fhat, out, mask, form);  \
+        case 4: return batch_w<T, 8>(T_, plans, fhat, out, mask, form);  \
+        case 5: return batch_w<T, 10>(T_, plans, fhat, out, mask, form); \
+        case 6: return batch_w<T, 12>(T_, plans, fhat, out, mask, form); \
+        case 7: return batch_w<T, 14>(T_, plans, fhat, out, mask, form); \
+        case 8: return batch_w<T, 16>(T_, plans, fhat, out, mask, form); \
         default: return NFFT3_ERR_INVALID_ARG;                    \
     }
 
 int launch_batch(int T_, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out, int mask,
-                 bool noalloc) {
+                 int form) {
     if (plans[0]->dtype == NFFT3_C128) { NFFT3_BATCH_M(double) }
     NFFT3_BATCH_M(float)
 }

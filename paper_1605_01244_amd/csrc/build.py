@@ -13,7 +13,8 @@ import sys
 CSRC = os.path.dirname(os.path.abspath(__file__))
 HERE = os.path.dirname(CSRC)
 LIB = os.path.join(HERE, "libnfft3.so")
-SOURCES = ["api.hip", "fft.hip", "points.hip", "interp.hip", "spread.hip", "batch.hip", "rgrid.hip", "infftm.hip", "gpe.hip"]
+SOURCES = ["api.hip", "fft.hip", "points.hip", "interp.hip", "spread.hip", "batch.hip", "rgrid.hip", "infftm.hip", "gpe.hip",
+           "queue_f32.hip", "queue_f64.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -283,8 +283,11 @@ int launch_fields(nfft3_plan_impl *p, const void *grid, void *out, int mask);
 int launch_spread(nfft3_plan_impl *p, const void *f, void *grid);
 int launch_zero(nfft3_plan_impl *p, void *buf, size_t bytes);
 // batch (batch.hip)
+// forms of the batch: per-length launches (descriptors in a library buffer or
+// in the static array), or one work-queue launch
+enum { kBatchLaunches = 0, kBatchNoAlloc = 1, kBatchQueue = 2 };
 int launch_batch(int T, nfft3_plan_impl *const *plans, const void *const *fhat, void *const *out,
-                 int deriv_mask, bool noalloc);
+                 int deriv_mask, int form);
 
 // exclusive scan of n ints (in -> out, out[n] = total; in place allowed);
 // sums holds ceil(n / 1024) ints (points.hip)
