@@ -214,7 +214,8 @@ def bench_batched(nf, torch, dev, workloads, stream):
     form (one launch per FFT stage and axis length plus one window-sum launch,
     each over all transforms of the batch: 256 in FP32, whose derivative
     fields are spectral; 64 in FP64, whose window sums also form the
-    derivative fields), timed with HIP events."""
+    derivative fields), and the same batch as one work-queue launch
+    (nfft3_batch_trafo_queue, `queue_ms_per_batch`), timed with HIP events."""
     t0 = time.time()
     sets = workloads.batched_sets(64)
     log(f"batched inputs generated in {time.time() - t0:.1f}s")
@@ -237,9 +238,21 @@ def bench_batched(nf, torch, dev, workloads, stream):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
+        qouts = nf.batch_trafo(plans, fh, 7, queue=True)
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in zip(outs, qouts))
+        e0.record(stream)
+        for _ in range(reps):
+            qouts = nf.batch_trafo(plans, fh, 7, queue=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        qms = e0.elapsed_time(e1) / reps
         evals = 4 * sum(p.M for p in plans)
-        res[form] = {"m": m, "ms_per_batch": ms, "point_evaluations_per_s": evals / (ms * 1e-3)}
-        log(f"batched {form}: {ms:.2f} ms per batch of 64 sets x 4 fields ({evals / ms * 1e3:.3e} evaluations/s)")
+        res[form] = {"m": m, "ms_per_batch": ms, "point_evaluations_per_s": evals / (ms * 1e-3),
+                     "queue_ms_per_batch": qms, "queue_equals_launches": bool(same)}
+        log(f"batched {form}: {ms:.2f} ms per batch of 64 sets x 4 fields ({evals / ms * 1e3:.3e} evaluations/s); "
+            f"one work-queue launch {qms:.2f} ms (bit-equal: {same})")
+        del qouts
         for p in plans:
             p.close()
         del plans, fh, outs

@@ -217,6 +217,11 @@ def test_batched_64_sets_with_derivative_fields(nf, dtype, m):
     for t in (0, 1, 17, 40, 63):
         seq = plans[t].trafo_fields(fh[t], 7)
         assert torch.equal(outs[t], seq), t
+    # the same batch as one work-queue launch: the same bits
+    qouts = nf.batch_trafo(plans, fh, 7, queue=True)
+    for t in range(len(plans)):
+        assert torch.equal(qouts[t], outs[t]), t
+    del qouts
     gate = tol(m, 2.0, dtype)
     worst = 0.0
     for t, (N, f, x) in enumerate(sets):
