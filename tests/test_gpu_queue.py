@@ -75,6 +75,31 @@ def test_queue_many_transforms_repeated(nf):
             assert np.array_equal(outs[t].cpu().numpy(), ref[t]), (rep, t)
 
 
+@pytest.mark.parametrize("dtype,m,pts", [("c64", 4, 256), ("c128", 8, 512), ("c64", 2, 512), ("c128", 5, 256)])
+def test_queue_tunings_and_window_widths(nf, dtype, m, pts):
+    """Per-plan tiles (8 / 20 / 32 cells) and both item sizes (256 points:
+    one per thread; 512: two), at several m: the queue equals the per-length
+    launches bit for bit and meets the oracle gate."""
+    spec = [((32, 32, 32), 2500), ((40, 48, 32), 1500), ((64, 40, 48), 3000)]
+    sets, plans, fh = [], [], []
+    for i, ((N, M), tile) in enumerate(zip(spec, (8, 20, 32))):
+        f, x = rand_coeffs(N, 1100 + i), rand_points(M, 1200 + i)
+        p = nf.Plan(N, sigma=2.0, m=m, dtype=torch_dtype(dtype), device="cuda:0")
+        p.set_tuning(tile, pts)
+        p.set_points(to_dev(x))
+        sets.append((N, f, x))
+        plans.append(p)
+        fh.append(to_dev(f, dtype))
+    log(f"queue {dtype} m={m} items of {pts} points, tiles 8 / 20 / 32")
+    ref = nf.batch_trafo(plans, fh, 5)
+    outs = nf.batch_trafo(plans, fh, 5, queue=True)
+    for t, (N, f, x) in enumerate(sets):
+        got = outs[t].cpu().numpy()
+        assert np.array_equal(got, ref[t].cpu().numpy()), t
+        l2, li = rel(got[0], oracle.ndft_trafo(f, x))
+        assert l2 <= tol(m, 2.0, dtype) and li <= tol(m, 2.0, dtype), (t, l2, li)
+
+
 def test_queue_wait_limit_abort_then_recovers(nf):
     """With a zero wait limit any task that finds its previous stage still
     running abandons the batch: the call returns NFFT3_ERR_TIMEOUT (or, if no
