@@ -51,9 +51,9 @@ batch_rows_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids
                   int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int g = batch_find(first, X, blockIdx.x);
-    const BatchXform &b = xf[ids[g]];
-    if constexpr (L == 0) rows_body<T, 0, kBRowThreads>(b.rows, blockIdx.x - first[g], smem_raw);
-    else rows_body_s<T, 0, kBRowThreads, L, static_rows_nl<T>(L)>(b.rows, blockIdx.x - first[g], smem_raw);
+    const RowArgs a = load_rows(&((cbx_t *)xf)[ids[g]].rows);
+    if constexpr (L == 0) rows_body<T, 0, kBRowThreads>(a, blockIdx.x - first[g], smem_raw);
+    else rows_body_s<T, 0, kBRowThreads, L, static_rows_nl<T>(L)>(a, blockIdx.x - first[g], smem_raw);
 }
 
 template <typename T, int AXIS, int L>
@@ -62,10 +62,10 @@ batch_cols_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ ids
                   int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int g = batch_find(first, X, blockIdx.x);
-    const BatchXform &b = xf[ids[g]];
+    cbx_t *b = (cbx_t *)xf + ids[g];
     const int tile = blockIdx.x - first[g];
-    const ColArgs &c = AXIS == 1 ? b.c1 : b.c0;
-    const int gx = AXIS == 1 ? b.gx1 : b.gx0;
+    const ColArgs c = load_cols(AXIS == 1 ? &b->c1 : &b->c0);
+    const int gx = AXIS == 1 ? b->gx1 : b->gx0;
     if constexpr (L == 0) cols_body<T, true, kColsThreadsGeneric, 16>(c, tile % gx, tile / gx, smem_raw);
     else cols_body_s<T, true, kColsThreads, L, static_cols_nl<T>(L)>(c, tile % gx, tile / gx, smem_raw);
 }
@@ -76,7 +76,7 @@ batch_interp_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ i
                     int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int g = batch_find(first, X, blockIdx.x);
-    interp_body<T, W, PPT>(xf[ids[g]].ip, blockIdx.x - first[g], smem_raw);
+    interp_body<T, W, PPT>(load_ps(&((cbx_t *)xf)[ids[g]].ip), blockIdx.x - first[g], smem_raw);
 }
 
 // complex<double> with derivative fields: the field and its derivative fields
@@ -87,7 +87,7 @@ batch_fields_kernel(const BatchXform *__restrict__ xf, const int *__restrict__ i
                     int X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int g = batch_find(first, X, blockIdx.x);
-    interp_body_der<T, W, kModeFields>(xf[ids[g]].ip, blockIdx.x - first[g], smem_raw);
+    interp_body_der<T, W, kModeFields>(load_ps(&((cbx_t *)xf)[ids[g]].ip), blockIdx.x - first[g], smem_raw);
 }
 
 // one launch of a stage over one group of transforms

@@ -20,6 +20,74 @@ struct BatchXform {
     int ntile[kStages];
 };
 
+// ------------------------------------------------ descriptor loads ----
+// Both forms read their descriptors from a device table.  The helpers below
+// read them as uniform (scalar) values through the constant address space
+// and keep their pointers marked as global memory, so that the stage bodies
+// compile to global (not flat) accesses with uniform control flow, whether
+// they are inlined into a kernel or called.
+typedef __attribute__((address_space(4))) const BatchXform cbx_t;
+
+// a copy of *p read as uniform (scalar) values
+template <class S>
+__device__ __forceinline__ S load_uniform(__attribute__((address_space(4))) const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "descriptor size");
+    S v;
+    const __attribute__((address_space(4))) int *src = (const __attribute__((address_space(4))) int *)p;
+    int *dst = reinterpret_cast<int *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
+    return v;
+}
+
+// A descriptor pointer field reloaded as a global-memory pointer (the
+// word-wise copy above loses that): accesses through it then compile to
+// global, not flat, instructions, and loads at uniform addresses stay
+// uniform.
+template <class P>
+__device__ __forceinline__ P *gptr_at(const __attribute__((address_space(4))) void *loc) {
+    typedef __attribute__((address_space(1))) P *gptr;
+    return (P *)*(const __attribute__((address_space(4))) gptr *)loc;
+}
+__device__ __forceinline__ RowArgs load_rows(__attribute__((address_space(4))) const RowArgs *src) {
+    RowArgs a = load_uniform(src);
+    a.in = gptr_at<const void>(&src->in);
+    a.out = gptr_at<void>(&src->out);
+    a.c0 = gptr_at<const void>(&src->c0);
+    a.c1 = gptr_at<const void>(&src->c1);
+    a.c2 = gptr_at<const void>(&src->c2);
+    a.tw = gptr_at<const void>(&src->tw);
+    a.stw = gptr_at<const void>(&src->stw);
+    return a;
+}
+__device__ __forceinline__ ColArgs load_cols(__attribute__((address_space(4))) const ColArgs *src) {
+    ColArgs a = load_uniform(src);
+    a.data = gptr_at<void>(&src->data);
+    a.tw = gptr_at<const void>(&src->tw);
+    a.stw = gptr_at<const void>(&src->stw);
+    return a;
+}
+__device__ __forceinline__ PSArgs load_ps(__attribute__((address_space(4))) const PSArgs *src) {
+    PSArgs a = load_uniform(src);
+    a.xs = gptr_at<const double>(&src->xs);
+    a.perm = gptr_at<const int>(&src->perm);
+    a.items = gptr_at<const int4>(&src->items);
+    a.grid = gptr_at<const void>(&src->grid);
+    a.grid_out = gptr_at<void>(&src->grid_out);
+    a.vals = gptr_at<const void>(&src->vals);
+    a.out = gptr_at<void>(&src->out);
+    a.coef = gptr_at<const void>(&src->coef);
+    return a;
+}
+
+// the descriptor table as a uniform constant-address pointer
+__device__ __forceinline__ cbx_t *uniform_xf(const BatchXform *xf) {
+    const uint64_t pa = (uint64_t)xf;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)pa);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
+    return (cbx_t *)(((uint64_t)hi << 32) | lo);
+}
+
 // ------------------------------------------------------- work queue ----
 // The work-queue form runs the whole batch as one launch of persistent
 // workgroups that take tickets 0, 1, ... from a counter.  The tickets are

@@ -30,34 +30,12 @@
 
 namespace nfft3 {
 
-typedef __attribute__((address_space(4))) const BatchXform cbx_t;
-
-// a copy of *p read as uniform (scalar) values
-template <class S>
-__device__ __forceinline__ S load_uniform(__attribute__((address_space(4))) const S *p) {
-    static_assert(sizeof(S) % 4 == 0, "descriptor size");
-    S v;
-    const __attribute__((address_space(4))) int *src = (const __attribute__((address_space(4))) int *)p;
-    int *dst = reinterpret_cast<int *>(&v);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
-    return v;
-}
-
-// the descriptor table as a uniform constant-address pointer
-__device__ __forceinline__ cbx_t *uniform_xf(const BatchXform *xf) {
-    const uint64_t pa = (uint64_t)xf;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)pa);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
-    return (cbx_t *)(((uint64_t)hi << 32) | lo);
-}
-
 template <typename T, int L>
 __device__ __attribute__((noinline)) void q_rows(const BatchXform *xf_, int x_, int blk_) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cbx_t *xf = uniform_xf(xf_);
     const int x = __builtin_amdgcn_readfirstlane(x_), blk = __builtin_amdgcn_readfirstlane(blk_);
-    const RowArgs a = load_uniform(&xf[x].rows);
+    const RowArgs a = load_rows(&xf[x].rows);
     rows_body_s<T, 0, kQThreads, L, static_rows_nl<T>(L)>(a, blk, smem_raw);
 }
 
@@ -67,7 +45,7 @@ __device__ __attribute__((noinline)) void q_cols(const BatchXform *xf_, int x_, 
     cbx_t *xf = uniform_xf(xf_);
     const int x = __builtin_amdgcn_readfirstlane(x_), tile = __builtin_amdgcn_readfirstlane(tile_);
     const bool a1 = __builtin_amdgcn_readfirstlane(axis_) == 1;
-    const ColArgs c = load_uniform(a1 ? &xf[x].c1 : &xf[x].c0);
+    const ColArgs c = load_cols(a1 ? &xf[x].c1 : &xf[x].c0);
     const int gx = a1 ? xf[x].gx1 : xf[x].gx0;
     cols_body_s<T, true, kQThreads, L, queue_cols_nl<T>(L)>(c, tile % gx, tile / gx, smem_raw);
 }
@@ -178,7 +156,7 @@ __device__ __forceinline__ void queue_body(const QueueArgs &q) {
             // the window sums: nothing waits for them (the kernel's end
             // publishes the outputs)
             cbx_t *xf = uniform_xf(q.xf);
-            const PSArgs a = load_uniform(&xf[sg.x].ip);
+            const PSArgs a = load_ps(&xf[sg.x].ip);
             for (int task = c0; task < c1; ++task) {
                 if (task > c0) __syncthreads();
                 if constexpr (FIELDS) interp_body_der<T, W, kModeFields>(a, task, smem_raw);
