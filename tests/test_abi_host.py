@@ -90,9 +90,13 @@ def test_null_handling(nf):
     assert lib.nfft3_set_tuning(None, 16, 256) == -7
     assert lib.nfft3_get_tuning(None, None, None) == -7
     assert lib.nfft3_autotune(None, 0, None, None, None, 1, None, None) == -7
-    assert lib.nfft3_batch_trafo(-1, None, None, None, 0) == -1
-    assert lib.nfft3_batch_trafo(0, None, None, None, 0) == 0
+    for batch in (lib.nfft3_batch_trafo, lib.nfft3_batch_trafo_noalloc, lib.nfft3_batch_trafo_queue):
+        assert batch(-1, None, None, None, 0) == -1          # negative count
+        assert batch(0, None, None, None, 0) == 0            # empty batch: nothing to do
+        assert batch(1, None, None, None, 0) == -7           # NULL arrays
+        assert batch(1, None, None, None, 8) == -1           # mask beyond the three axes
     assert lib.nfft3_strerror(-5) == b"non-finite point coordinate"
+    assert b"time limit" in lib.nfft3_strerror(-9)
 
 
 def test_deconv_factors_match_textbook_pair(nf):
