@@ -189,7 +189,7 @@ int nfft3_batch_trafo(int T, const nfft3_plan_t *plans, const void *const *fhat_
  * be ones the library's compile-time FFT engine covers (64, 80, 96, 128,
  * 160, 192, 256, 320, 384, 512), else NFFT3_ERR_INVALID_ARG before any work.
  * Each wait is bounded by NFFT3_QUEUE_WAIT_US microseconds of wall clock
- * (environment, read per call; default 2000000): a wait past it abandons the
+ * (environment, read per call; default 2000000, at most 3.6e9): a wait past it abandons the
  * batch (the outputs are then incomplete) and returns NFFT3_ERR_TIMEOUT.
  * Allocates its descriptor buffer as nfft3_batch_trafo does (shared with it,
  * under the same per-GPU lock); synchronises before it returns. */

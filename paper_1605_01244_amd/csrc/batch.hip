@@ -175,12 +175,12 @@ __global__ void __launch_bounds__(256) queue_reset_kernel(unsigned *ctl, int n) 
 }
 
 // wall-clock ticks a queue wait may last: NFFT3_QUEUE_WAIT_US microseconds
-// (default 2 s)
+// (default 2 s, at most one hour)
 static int queue_wait_ticks(int dev, unsigned long long *ticks) {
     int khz = 0;
     NFFT3_HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     double us = 2e6;
-    if (const char *e = std::getenv("NFFT3_QUEUE_WAIT_US")) us = std::max(0.0, std::atof(e));
+    if (const char *e = std::getenv("NFFT3_QUEUE_WAIT_US")) us = std::min(std::max(0.0, std::atof(e)), 3.6e9);
     *ticks = (unsigned long long)(us * 1e-3 * (double)std::max(khz, 1));
     return NFFT3_OK;
 }
