@@ -92,31 +92,41 @@ struct GemmArgs {
     int64_t tiles_m, tiles_n;
 };
 
-constexpr int kGB = 64;        // C tile: 64 x 64, four waves of 32 x 32
+// C tile of a workgroup: BM x BN, four waves of BM/2 x BN/2 (2 x 2).  64 x
+// 64 (2 x 2 blocks per wave, two waves per SIMD) ran the 256^3 -> 321^3
+// chain fastest: 128 x 128 (FP32) and 128 x 64 (FP64) tiles, with four
+// times the operand reuse per LDS read, hold one wave per SIMD and took
+// 1.79 / 3.21 ms against 1.57 / 3.03 ms.
+template <typename T> struct GemmTile;
+template <> struct GemmTile<double> { static constexpr int BM = 64, BN = 64; };
+template <> struct GemmTile<float> { static constexpr int BM = 64, BN = 64; };
 constexpr int kGK = 16;        // contraction depth per LDS stage
 constexpr int kGThreads = 256;
 constexpr int kGPad = 1;       // LDS row padding (elements)
 
-// One workgroup per (batch, row tile, column tile).  The A tile (64 x 16) and
-// B tile (16 x 64) are staged in LDS as separate real and imaginary planes,
+// One workgroup per (batch, row tile, column tile).  The A tile (BM x 16) and
+// B tile (16 x BN) are staged in LDS as separate real and imaginary planes,
 // A transposed (k-major) so that the 16 lanes of an MFMA operand row read
 // consecutive words; the next K stage is loaded into registers while the
-// current one is consumed.  Wave w owns the 32 x 32 quadrant (w / 2, w % 2):
-// 2 x 2 MFMA blocks of 16 x 16, each with the three accumulators P1, P2, P3
-// (operand and result layouts: see Mfma).
-template <typename T>
+// current one is consumed.  Wave w owns the BM/2 x BN/2 quadrant (w / 2,
+// w % 2): IB x JB MFMA blocks of 16 x 16, each with the three accumulators
+// P1, P2, P3 (operand and result layouts: see Mfma); every operand read from
+// LDS feeds JB (A) or IB (B) blocks.
+template <typename T, int BM, int BN>
 __global__ void __launch_bounds__(kGThreads) rgrid_gemm_kernel(GemmArgs g) {
     using C2 = c_t<T>;
     using Acc = typename Mfma<T>::acc;
-    __shared__ T As[2][kGK][kGB + kGPad];   // [re/im][k][row]
-    __shared__ T Bs[2][kGK][kGB + kGPad];   // [re/im][k][col]
+    constexpr int IB = BM / 32, JB = BN / 32;
+    constexpr int QA = BM * kGK / kGThreads, QB = BN * kGK / kGThreads;
+    __shared__ T As[2][kGK][BM + kGPad];   // [re/im][k][row]
+    __shared__ T Bs[2][kGK][BN + kGPad];   // [re/im][k][col]
 
     const int64_t tiles = g.tiles_m * g.tiles_n;
     const int64_t bidx = blockIdx.x;
     const int64_t batch = bidx / tiles;
     const int64_t rem = bidx - batch * tiles;
     const int64_t tm = rem / g.tiles_n, tn = rem - tm * g.tiles_n;
-    const int64_t row0 = tm * kGB, col0 = tn * kGB;
+    const int64_t row0 = tm * BM, col0 = tn * BN;
     const C2 *A = (const C2 *)g.A + batch * g.sa;
     const C2 *B = (const C2 *)g.B + batch * g.sb;
     C2 *C = (C2 *)g.C + batch * g.sc;
@@ -124,49 +134,57 @@ __global__ void __launch_bounds__(kGThreads) rgrid_gemm_kernel(GemmArgs g) {
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * (BN / 2);
 
-    // register staging: 4 A and 4 B elements per thread per stage
-    C2 ra[4], rb[4];
+    // register staging: QA A and QB B elements per thread per stage
+    C2 ra[QA], rb[QB];
     auto load_stage = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QA; ++q) {
             const int e = t + q * kGThreads;
-            const int ar = e >> 4, ak = e & 15;          // A: 64 rows x 16 k
+            const int ar = e >> 4, ak = e & 15;          // A: BM rows x 16 k
             const int64_t gr = row0 + ar, gk = k0 + ak;
             ra[q] = (gr < g.M && gk < g.K) ? A[gr * g.lda + gk] : cmk<T>((T)0, (T)0);
-            const int bk = e >> 6, bc = e & 63;          // B: 16 k x 64 cols
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = t + q * kGThreads;
+            const int bk = e / BN, bc = e % BN;          // B: 16 k x BN cols
             const int64_t hk = k0 + bk, hc = col0 + bc;
             rb[q] = (hk < g.K && hc < g.N) ? B[hk * g.ldb + hc] : cmk<T>((T)0, (T)0);
         }
     };
     auto store_stage = [&]() {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QA; ++q) {
             const int e = t + q * kGThreads;
             const int ar = e >> 4, ak = e & 15;
             As[0][ak][ar] = ra[q].x;
             As[1][ak][ar] = ra[q].y;
-            const int bk = e >> 6, bc = e & 63;
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = t + q * kGThreads;
+            const int bk = e / BN, bc = e % BN;
             Bs[0][bk][bc] = rb[q].x;
             Bs[1][bk][bc] = rb[q].y;
         }
     };
 
-    Acc p1[2][2], p2[2][2], p3[2][2];
+    Acc p1[IB][JB], p2[IB][JB], p3[IB][JB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < JB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { p1[i][j][r] = 0; p2[i][j][r] = 0; p3[i][j][r] = 0; }
     // 16 x 16 blocks wholly outside C (in the last row or column tile) issue
     // no MFMAs: a 321-wide output then costs 21 blocks per axis, not 24
-    bool live[2][2];
+    bool live[IB][JB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) live[i][j] = row0 + wr + i * 16 < g.M && col0 + wc + j * 16 < g.N;
+        for (int j = 0; j < JB; ++j) live[i][j] = row0 + wr + i * 16 < g.M && col0 + wc + j * 16 < g.N;
 
     load_stage(0);
     for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
@@ -176,20 +194,23 @@ __global__ void __launch_bounds__(kGThreads) rgrid_gemm_kernel(GemmArgs g) {
         if (k0 + kGK < g.K) load_stage(k0 + kGK);
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 4) {
-            T a_r[2], a_i[2], a_s[2], b_r[2], b_i[2], b_s[2];
+            T a_r[IB], a_i[IB], a_s[IB], b_r[JB], b_i[JB], b_s[JB];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < IB; ++i) {
                 a_r[i] = As[0][kk + lk][wr + i * 16 + lr];
                 a_i[i] = As[1][kk + lk][wr + i * 16 + lr];
                 a_s[i] = a_r[i] + a_i[i];
-                b_r[i] = Bs[0][kk + lk][wc + i * 16 + lr];
-                b_i[i] = Bs[1][kk + lk][wc + i * 16 + lr];
-                b_s[i] = b_r[i] + b_i[i];
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < JB; ++j) {
+                b_r[j] = Bs[0][kk + lk][wc + j * 16 + lr];
+                b_i[j] = Bs[1][kk + lk][wc + j * 16 + lr];
+                b_s[j] = b_r[j] + b_i[j];
+            }
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+            for (int i = 0; i < IB; ++i)
+#pragma unroll
+                for (int j = 0; j < JB; ++j) {
                     if (!live[i][j]) continue;
                     p1[i][j] = Mfma<T>::fma(a_r[i], b_r[j], p1[i][j]);
                     p2[i][j] = Mfma<T>::fma(a_i[i], b_i[j], p2[i][j]);
@@ -198,9 +219,9 @@ __global__ void __launch_bounds__(kGThreads) rgrid_gemm_kernel(GemmArgs g) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < JB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gr = row0 + wr + i * 16 + Mfma<T>::row(lk, r);
@@ -219,11 +240,12 @@ static int launch_gemm(hipStream_t s, const void *A, const void *B, void *C, int
     g.M = M; g.N = N; g.K = K;
     g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.sa = sa; g.sb = sb; g.sc = sc;
-    g.tiles_m = (M + kGB - 1) / kGB;
-    g.tiles_n = (N + kGB - 1) / kGB;
+    constexpr int BM = GemmTile<T>::BM, BN = GemmTile<T>::BN;
+    g.tiles_m = (M + BM - 1) / BM;
+    g.tiles_n = (N + BN - 1) / BN;
     const int64_t blocks = g.tiles_m * g.tiles_n * batch;
     if (blocks > (int64_t)INT32_MAX) return NFFT3_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(rgrid_gemm_kernel<T>, dim3((unsigned)blocks), dim3(kGThreads), 0, s, g);
+    hipLaunchKernelGGL((rgrid_gemm_kernel<T, BM, BN>), dim3((unsigned)blocks), dim3(kGThreads), 0, s, g);
     NFFT3_LAUNCH_CHECK("rgrid_gemm_kernel");
     return NFFT3_OK;
 }
